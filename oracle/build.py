@@ -1,0 +1,24 @@
+"""Build step for the oracle's C library (test infrastructure only).
+
+Compiles ``radic_oracle.c`` with gcc into ``liboracle.so`` next to this file.
+Plain -O2, no fast-math, so IEEE semantics are kept.
+"""
+import os
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "radic_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-std=c11", "-fno-fast-math", "-fPIC", "-shared", "-pthread",
+           "-Wall", "-Wextra", "-o", LIB, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))
