@@ -1,0 +1,263 @@
+/*
+ * radic.h -- C ABI of the MI355X (gfx950) Radic-determinant library.
+ *
+ * The Radic determinant of a real m x n matrix A with m <= n (Definition 3,
+ * eq. (1) of Abdollahi, Jafari, Bayat, Amiri and Fathy, "An efficient parallel
+ * algorithm for computing determinant of non-square matrices based on Radic's
+ * definition"):
+ *
+ *     det(A) = sum over 1 <= j1 < ... < jm <= n of (-1)^(r+s) det(A[:, j1..jm])
+ *     r = 1 + 2 + ... + m,   s = j1 + ... + jm   (1-based column indices),
+ *     det(A) = 0 when m > n.
+ *
+ * The library evaluates the sum the way the paper's parallel algorithm does
+ * (Sections 4-5): every GPU lane unranks its first column sequence in dictionary
+ * order, walks a contiguous range of ranks with the dictionary successor, gathers
+ * each m x m minor, factors it by LU with partial pivoting (FP64, or FP32 with an
+ * FP64 rerun of badly conditioned minors) or by fraction-free elimination modulo
+ * 31-bit primes (integers), and feeds a compensated wave -> block -> grid tree
+ * reduction (the CREW tree sum of Section 6).
+ *
+ * Conventions shared by every entry point
+ *  - Every function is extern "C", never throws and never aborts.
+ *  - Pointers named d* are device memory, h* are host memory.  The caller owns
+ *    every buffer; the library allocates no device memory per call.  Scratch
+ *    space is the caller's workspace (size from radic_workspace_bytes), which
+ *    must be 256-byte aligned and must not be shared by calls that may overlap.
+ *  - Matrices are row-major with leading dimension lda >= n (elements).
+ *  - Work is enqueued on `stream` (0 = the null stream).  Functions documented
+ *    as asynchronous return after enqueueing; their device-side result,
+ *    including the device-detected status, is valid once the stream reaches
+ *    that point.  Nothing here uses stream priorities.
+ *  - Return values are radic_status codes for host-detected conditions.
+ *  - Limits: 1 <= m <= RADIC_MAX_M, n <= RADIC_MAX_N, C(n, m) < 2^63.
+ */
+#ifndef RADIC_H
+#define RADIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RADIC_MAX_M 12
+#define RADIC_MAX_N 1024
+#define RADIC_MAX_PRIMES 24
+
+typedef enum {
+    RADIC_OK = 0,
+    RADIC_EINVAL = -1,      /* null pointer, m < 1, n < 1, lda < n, bad enum */
+    RADIC_ENOTSUP = -2,     /* m > RADIC_MAX_M, n > RADIC_MAX_N, shape too big for on-chip staging */
+    RADIC_EOVERFLOW = -3,   /* C(n, m) >= 2^63, or an output buffer too small for the exact result */
+    RADIC_ENOMEM = -4,      /* host allocation failed (library bookkeeping only) */
+    RADIC_EDEVICE = -5,     /* a HIP call failed */
+    RADIC_EWORKSPACE = -6,  /* workspace null, misaligned or smaller than radic_workspace_bytes */
+    RADIC_ENONFINITE = -7   /* a NaN or infinity in a floating-point input (device-detected) */
+} radic_status;
+
+typedef enum {
+    RADIC_FP64 = 0,      /* every minor factored in IEEE double */
+    RADIC_FP32_BULK = 1  /* minors factored in float on rows pre-scaled by exact powers of two;
+                            minors with a pivot below tau * (column scale) are refactored in
+                            double; all accumulation in double */
+} radic_precision;
+
+/* Workspace kinds for radic_workspace_bytes. */
+typedef enum {
+    RADIC_WS_DET = 0,      /* radic_det, radic_det_subsets */
+    RADIC_WS_INT = 1,      /* radic_det_int_exact */
+    RADIC_WS_BATCHED = 2   /* radic_det_batched */
+} radic_ws_kind;
+
+/* Result of a floating-point Radic determinant (written to device memory).
+ * value   = hi + lo rounded to double: the signed sum of eq. (1).
+ * hi, lo  = unevaluated double-double sum (|lo| <= ulp(hi)/2 after normalisation).
+ * abs_sum = sum of |det(A_J)| over the same subsets (the tolerance normaliser).
+ * n_subsets  = number of minors evaluated (C(n, m), or the requested rank count).
+ * n_fallback = FP32_BULK only: minors refactored in double.
+ * status  = RADIC_OK, or RADIC_ENONFINITE (then value is NaN). */
+typedef struct {
+    double value;
+    double hi;
+    double lo;
+    double abs_sum;
+    uint64_t n_subsets;
+    uint64_t n_fallback;
+    int32_t status;
+    int32_t reserved;
+} radic_f64_result;
+
+/* One matrix of a batch.  dtype 0: float64 entries at dF64 + offset; dtype 1: int32
+ * entries at dI32 + offset (offset and lda in elements of that type). */
+typedef struct {
+    int32_t m;
+    int32_t n;
+    int32_t dtype;
+    int32_t reserved;
+    int64_t offset;
+    int64_t lda;
+} radic_matrix_desc;
+
+/* Per-matrix result of a batch (device memory).
+ * Float matrices: value/hi/lo/abs_sum/n_fallback as in radic_f64_result.
+ * Integer matrices: the exact result is sign * sum_i mag[i] 2^(32 i) with
+ * mag_len significant little-endian limbs; value is that integer rounded to double.
+ * status: per-matrix radic_status (EINVAL/ENOTSUP for a bad descriptor,
+ * EOVERFLOW when the exact result needs more than 24 limbs, ENONFINITE). */
+typedef struct {
+    double value;
+    double hi;
+    double lo;
+    double abs_sum;
+    uint64_t n_subsets;
+    uint64_t n_fallback;
+    int32_t status;
+    int32_t sign;
+    int32_t mag_len;
+    int32_t n_primes;
+    uint32_t mag[RADIC_MAX_PRIMES];
+} radic_batch_result;
+
+/* Human-readable name of a status code (static string). */
+const char *radic_status_string(int status);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int radic_version(void);
+
+/* Bytes of device workspace needed by one call of the given kind.
+ * RADIC_WS_DET / RADIC_WS_INT: for an m x n matrix (batch ignored).
+ * RADIC_WS_BATCHED: for `batch` matrices (m, n ignored).
+ * Returns 0 for invalid arguments. */
+size_t radic_workspace_bytes(int kind, int m, int n, int batch);
+
+/*
+ * radic_det -- Radic determinant of one float64 matrix (Definition 3, eq. (1)),
+ * evaluated over all C(n, m) column sequences in dictionary order.
+ *   dA     device, m x n float64, row-major, leading dimension lda (elements).
+ *   prec   RADIC_FP64 or RADIC_FP32_BULK.
+ *   dOut   device, one radic_f64_result.
+ *   dWork  device workspace of at least radic_workspace_bytes(RADIC_WS_DET, m, n, 0) bytes.
+ * Asynchronous.  m > n writes value 0 (Definition 3) and returns RADIC_OK.
+ * Errors: EINVAL, ENOTSUP, EOVERFLOW, EWORKSPACE, EDEVICE (nothing enqueued
+ * except for EDEVICE).  Non-finite entries give dOut->status = ENONFINITE.
+ */
+int radic_det(const double *dA, int m, int n, int64_t lda, int prec, radic_f64_result *dOut,
+              void *dWork, size_t work_bytes, hipStream_t stream);
+
+/*
+ * radic_det_range -- as radic_det, restricted to the dictionary ranks
+ * [q_begin, q_begin + count) (count clipped to C(n, m) - q_begin).  This is one
+ * processor's share in the granularity scheme of Section 5 (and one GPU's share
+ * when the rank space is split across devices).  dOut->n_subsets = ranks done.
+ */
+int radic_det_range(const double *dA, int m, int n, int64_t lda, int prec, uint64_t q_begin,
+                    uint64_t count, radic_f64_result *dOut, void *dWork, size_t work_bytes,
+                    hipStream_t stream);
+
+/*
+ * radic_det_subsets -- export the individual signed terms of eq. (1):
+ * dTerms[t] = (-1)^(r+s) det(A_J) of the dictionary rank q_begin + t, for
+ * t < count, computed like radic_det in the given precision (FP32_BULK terms are
+ * rounded float results widened to double, or the double refactorisation when
+ * the fallback fires).  Optional dCols (may be null) receives the m 1-based column
+ * indices of each sequence as uint8 (requires n <= 255), row t at dCols + t*m.
+ * Asynchronous; no workspace.  count must be <= 2^31.
+ */
+int radic_det_subsets(const double *dA, int m, int n, int64_t lda, int prec, uint64_t q_begin,
+                      uint64_t count, double *dTerms, uint8_t *dCols, hipStream_t stream);
+
+/*
+ * radic_det_int_exact -- exact Radic determinant of one int32 matrix.
+ * Each minor is eliminated fraction-free modulo k 31-bit primes (k chosen on the
+ * device from a Hadamard-type bound so that the product of the primes exceeds
+ * twice the largest possible |result|), residues are summed per prime and
+ * combined by Garner's mixed-radix CRT into a signed integer.
+ *   hMag       host, capacity mag_capacity little-endian 32-bit limbs of |result|.
+ *   hMagLen    host, number of significant limbs written (0 for a zero result);
+ *              on RADIC_EOVERFLOW the number of limbs needed.
+ *   hSign      host, -1, 0 or +1.
+ * Synchronous: returns after the result is in host memory.
+ * Errors: EINVAL, ENOTSUP, EOVERFLOW (C(n,m) too large, or mag_capacity too small),
+ * EWORKSPACE, EDEVICE.
+ */
+int radic_det_int_exact(const int32_t *dA, int m, int n, int64_t lda, uint32_t *hMag,
+                        int mag_capacity, int *hMagLen, int *hSign, void *dWork, size_t work_bytes,
+                        hipStream_t stream);
+
+/*
+ * radic_det_batched -- Radic determinants of `batch` matrices of mixed shapes and
+ * types in one persistent kernel.  The rank spaces of all matrices are cut into
+ * chunks; resident workgroups take chunks from one global atomic queue (the
+ * granularity scheme of Section 5 applied to the whole batch); float matrices use
+ * `prec`, int32 matrices use the exact multi-modular path.  Per-matrix partial
+ * sums are reduced in a fixed order, so results do not depend on scheduling.
+ *   dDesc  device, batch descriptors.   dF64 / dI32  device entry pools (either may
+ *          be null if no descriptor uses it).   dOut  device, batch results.
+ * Asynchronous and capturable into a HIP graph (no allocation, no host
+ * synchronisation, no memset nodes).  Bad descriptors are reported per matrix.
+ */
+int radic_det_batched(const radic_matrix_desc *dDesc, int batch, const double *dF64,
+                      const int32_t *dI32, int prec, radic_batch_result *dOut, void *dWork,
+                      size_t work_bytes, hipStream_t stream);
+
+/*
+ * Captured launch of radic_det_batched: records the same work into a HIP graph
+ * once and replays it with a single launch.  *hGraph receives an opaque handle.
+ * Arguments are bound at creation; replaying reuses them (contents of the
+ * buffers may change between replays, shapes in dDesc may too as long as
+ * `batch` is unchanged).  radic_graph_launch enqueues one replay on `stream`.
+ */
+int radic_batched_graph_create(const radic_matrix_desc *dDesc, int batch, const double *dF64,
+                               const int32_t *dI32, int prec, radic_batch_result *dOut, void *dWork,
+                               size_t work_bytes, void **hGraph);
+int radic_graph_launch(void *hGraph, hipStream_t stream);
+int radic_graph_destroy(void *hGraph);
+
+/*
+ * Launch-shape tuning (the granularity knob of Section 5).  radic_autotune times
+ * candidate (subsets per lane, workgroup size) pairs for the given shape and
+ * precision on the current device with HIP events, on a synthetic matrix of
+ * that shape, and records the fastest for later calls.  Synchronous.
+ * kind: RADIC_WS_DET (prec applies), RADIC_WS_INT or RADIC_WS_BATCHED (m is the
+ * row count class, n ignored).  hBest (may be null) receives {subsets_per_lane,
+ * block_size}.  radic_tune_save/load persist the table as text.
+ */
+int radic_autotune(int kind, int m, int n, int prec, int *hBest, hipStream_t stream);
+int radic_tune_save(const char *path);
+int radic_tune_load(const char *path);
+/* Force a launch shape (0 = tuned/default) for subsequent calls; for tests and sweeps. */
+int radic_set_launch(int subsets_per_lane, int block_size);
+/* FP32_BULK fallback threshold tau (default 2^-10): a minor is refactored in double
+ * when some pivot |u_kk| < tau * s_k, s_k the largest |entry| of that minor's k-th
+ * column in the row-scaled matrix.  tau = 0 disables, tau = +inf refactors all. */
+int radic_set_fallback_tau(double tau);
+
+/*
+ * Timing hook for benchmarks: while enabled, the library records HIP events on
+ * the launch stream around every launch of its main enumeration kernels.
+ * radic_profile_read waits for them and returns the summed duration in ms and
+ * the number of launches since the last read, then clears.
+ */
+int radic_profile_enable(int on);
+int radic_profile_read(double *hTotalMs, int *hLaunches);
+/* Same, but returns each launch's duration (ms) in launch order: up to capacity
+ * values in hMs, *hCount = launches recorded (may exceed capacity; extra are
+ * dropped).  Clears like radic_profile_read. */
+int radic_profile_read_launches(double *hMs, int capacity, int *hCount);
+
+/* Host-side combinatorics used by the launchers, exported for testing:
+ * binomial with overflow detection (returns EOVERFLOW), dictionary-order
+ * unranking (1-based columns into hCols), and the i-th prime used by the exact path. */
+int radic_host_binomial(int a, int b, uint64_t *hOut);
+int radic_host_unrank(int m, int n, uint64_t q, int *hCols);
+int radic_host_prime(int i, uint32_t *hPrime);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RADIC_H */

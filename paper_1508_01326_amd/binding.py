@@ -1,0 +1,280 @@
+"""ctypes binding of ``libradic.so`` (argument marshalling only).
+
+Every function named like a C entry point takes PyTorch tensors for device
+buffers, passes raw pointers and the current HIP stream, and returns what the C
+call returns.  All arithmetic runs in the library's HIP kernels.  Loading fails
+loudly when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libradic.so")
+
+RADIC_OK = 0
+RADIC_EINVAL = -1
+RADIC_ENOTSUP = -2
+RADIC_EOVERFLOW = -3
+RADIC_ENOMEM = -4
+RADIC_EDEVICE = -5
+RADIC_EWORKSPACE = -6
+RADIC_ENONFINITE = -7
+
+RADIC_FP64 = 0
+RADIC_FP32_BULK = 1
+PRECISIONS = {"fp64": RADIC_FP64, "fp32_bulk": RADIC_FP32_BULK}
+
+RADIC_WS_DET = 0
+RADIC_WS_INT = 1
+RADIC_WS_BATCHED = 2
+
+RADIC_MAX_M = 12
+RADIC_MAX_N = 1024
+RADIC_MAX_PRIMES = 24
+
+F64_RESULT_DTYPE = np.dtype([("value", "<f8"), ("hi", "<f8"), ("lo", "<f8"), ("abs_sum", "<f8"),
+                             ("n_subsets", "<u8"), ("n_fallback", "<u8"), ("status", "<i4"),
+                             ("reserved", "<i4")])
+DESC_DTYPE = np.dtype([("m", "<i4"), ("n", "<i4"), ("dtype", "<i4"), ("reserved", "<i4"),
+                       ("offset", "<i8"), ("lda", "<i8")])
+BATCH_RESULT_DTYPE = np.dtype([("value", "<f8"), ("hi", "<f8"), ("lo", "<f8"), ("abs_sum", "<f8"),
+                               ("n_subsets", "<u8"), ("n_fallback", "<u8"), ("status", "<i4"),
+                               ("sign", "<i4"), ("mag_len", "<i4"), ("n_primes", "<i4"),
+                               ("mag", "<u4", (RADIC_MAX_PRIMES,))])
+assert F64_RESULT_DTYPE.itemsize == 56
+assert DESC_DTYPE.itemsize == 32
+assert BATCH_RESULT_DTYPE.itemsize == 160
+
+# (name, restype, argtypes) of every exported function
+_vp, _i, _i64, _u64, _sz, _d = (ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64,
+                                ctypes.c_size_t, ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_dp = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "radic_status_string": (ctypes.c_char_p, [_i]),
+    "radic_version": (_i, []),
+    "radic_workspace_bytes": (_sz, [_i, _i, _i, _i]),
+    "radic_det": (_i, [_vp, _i, _i, _i64, _i, _vp, _vp, _sz, _vp]),
+    "radic_det_range": (_i, [_vp, _i, _i, _i64, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
+    "radic_det_subsets": (_i, [_vp, _i, _i, _i64, _i, _u64, _u64, _vp, _vp, _vp]),
+    "radic_det_int_exact": (_i, [_vp, _i, _i, _i64, _u32p, _i, _ip, _ip, _vp, _sz, _vp]),
+    "radic_det_batched": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _sz, _vp]),
+    "radic_batched_graph_create": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _sz, ctypes.POINTER(_vp)]),
+    "radic_graph_launch": (_i, [_vp, _vp]),
+    "radic_graph_destroy": (_i, [_vp]),
+    "radic_autotune": (_i, [_i, _i, _i, _i, _ip, _vp]),
+    "radic_tune_save": (_i, [ctypes.c_char_p]),
+    "radic_tune_load": (_i, [ctypes.c_char_p]),
+    "radic_set_launch": (_i, [_i, _i]),
+    "radic_set_fallback_tau": (_i, [_d]),
+    "radic_profile_enable": (_i, [_i]),
+    "radic_profile_read": (_i, [_dp, _ip]),
+    "radic_profile_read_launches": (_i, [_dp, _i, _ip]),
+    "radic_host_binomial": (_i, [_i, _i, _u64p]),
+    "radic_host_unrank": (_i, [_i, _i, _u64, _ip]),
+    "radic_host_prime": (_i, [_i, _u32p]),
+}
+
+_lib = None
+
+
+class RadicError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = status_string(status) if _lib is not None else str(status)
+        super().__init__(f"{where}: {msg}" if where else msg)
+
+
+def lib():
+    """Load the HIP library (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with paper_1508_01326_amd/build.py "
+                              "(there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status):
+    return lib().radic_status_string(int(status)).decode()
+
+
+def _check(rc, where):
+    if rc != RADIC_OK:
+        raise RadicError(rc, where)
+
+
+# ------------------------------------------------------------------ torch plumbing
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _require_cuda(t, dtype, name):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}")
+
+
+def _matrix_args(A, dtype):
+    _require_cuda(A, dtype, "A")
+    if A.dim() != 2:
+        raise ValueError("A must be 2-D")
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major with unit column stride")
+    m, n = A.shape
+    lda = A.stride(0) if m > 1 else n
+    return m, n, lda
+
+
+def workspace(kind, m=0, n=0, batch=0, device=None):
+    torch = _torch()
+    nbytes = int(lib().radic_workspace_bytes(kind, m, n, batch))
+    if nbytes == 0:
+        raise RadicError(RADIC_EINVAL, "radic_workspace_bytes")
+    # torch's caching allocator returns 256-byte aligned blocks
+    return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+
+
+def new_f64_result(device=None):
+    torch = _torch()
+    return torch.zeros(F64_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device or "cuda")
+
+
+def read_f64_result(out):
+    raw = out.cpu().numpy().tobytes()
+    r = np.frombuffer(raw, dtype=F64_RESULT_DTYPE)[0]
+    return {k: (r[k].item()) for k in F64_RESULT_DTYPE.names if k != "reserved"}
+
+
+# ------------------------------------------------------------------ entry points
+def radic_det(A, precision="fp64", out=None, work=None, stream=None, sync=True):
+    """Radic determinant of a float64 CUDA matrix.  Returns the result dict
+    (sync=True) or the device result buffer (sync=False)."""
+    torch = _torch()
+    m, n, lda = _matrix_args(A, torch.float64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    out = out if out is not None else new_f64_result(A.device)
+    work = work if work is not None else workspace(RADIC_WS_DET, max(m, 1), max(n, 1), device=A.device)
+    rc = lib().radic_det(ctypes.c_void_p(A.data_ptr()), m, n, lda, prec, ctypes.c_void_p(out.data_ptr()),
+                         ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_handle(stream))
+    _check(rc, "radic_det")
+    if not sync:
+        return out
+    torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return read_f64_result(out)
+
+
+def radic_det_range(A, q_begin, count, precision="fp64", out=None, work=None, stream=None, sync=True):
+    torch = _torch()
+    m, n, lda = _matrix_args(A, torch.float64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    out = out if out is not None else new_f64_result(A.device)
+    work = work if work is not None else workspace(RADIC_WS_DET, max(m, 1), max(n, 1), device=A.device)
+    rc = lib().radic_det_range(ctypes.c_void_p(A.data_ptr()), m, n, lda, prec, int(q_begin), int(count),
+                               ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()),
+                               work.numel(), _stream_handle(stream))
+    _check(rc, "radic_det_range")
+    if not sync:
+        return out
+    torch.cuda.synchronize(A.device)
+    return read_f64_result(out)
+
+
+def radic_det_subsets(A, q_begin, count, precision="fp64", with_cols=False, stream=None):
+    """Signed terms (-1)^(r+s) det(A_J) for ranks [q_begin, q_begin+count) (and
+    the 1-based columns when with_cols).  Returns CPU numpy arrays."""
+    torch = _torch()
+    m, n, lda = _matrix_args(A, torch.float64)
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    terms = torch.empty(int(count), dtype=torch.float64, device=A.device)
+    cols = torch.empty(int(count) * m if with_cols else 1, dtype=torch.uint8, device=A.device)
+    rc = lib().radic_det_subsets(ctypes.c_void_p(A.data_ptr()), m, n, lda, prec, int(q_begin), int(count),
+                                 ctypes.c_void_p(terms.data_ptr()),
+                                 ctypes.c_void_p(cols.data_ptr()) if with_cols else None,
+                                 _stream_handle(stream))
+    _check(rc, "radic_det_subsets")
+    torch.cuda.synchronize(A.device)
+    t = terms.cpu().numpy()
+    if with_cols:
+        return t, cols.cpu().numpy().reshape(int(count), m)
+    return t
+
+
+def radic_det_int_exact(A, work=None, stream=None, cap=RADIC_MAX_PRIMES + 2):
+    """Exact Radic determinant of an int32 CUDA matrix; returns a Python int."""
+    torch = _torch()
+    m, n, lda = _matrix_args(A, torch.int32)
+    work = work if work is not None else workspace(RADIC_WS_INT, max(m, 1), max(n, 1), device=A.device)
+    mag = (ctypes.c_uint32 * cap)()
+    length, sign = ctypes.c_int(0), ctypes.c_int(0)
+    rc = lib().radic_det_int_exact(ctypes.c_void_p(A.data_ptr()), m, n, lda, mag, cap, ctypes.byref(length),
+                                   ctypes.byref(sign), ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                   _stream_handle(stream))
+    _check(rc, "radic_det_int_exact")
+    v = 0
+    for i in reversed(range(length.value)):
+        v = (v << 32) | int(mag[i])
+    return -v if sign.value < 0 else v
+
+
+def set_launch(subsets_per_lane=0, block_size=0):
+    _check(lib().radic_set_launch(int(subsets_per_lane), int(block_size)), "radic_set_launch")
+
+
+def set_fallback_tau(tau):
+    _check(lib().radic_set_fallback_tau(float(tau)), "radic_set_fallback_tau")
+
+
+def profile_enable(on=True):
+    _check(lib().radic_profile_enable(1 if on else 0), "radic_profile_enable")
+
+
+def profile_read():
+    ms, launches = ctypes.c_double(0.0), ctypes.c_int(0)
+    _check(lib().radic_profile_read(ctypes.byref(ms), ctypes.byref(launches)), "radic_profile_read")
+    return ms.value, launches.value
+
+
+def profile_read_launches(capacity=4096):
+    buf = (ctypes.c_double * capacity)()
+    count = ctypes.c_int(0)
+    _check(lib().radic_profile_read_launches(buf, capacity, ctypes.byref(count)), "radic_profile_read_launches")
+    return [buf[i] for i in range(min(count.value, capacity))]
+
+
+def host_binomial(a, b):
+    out = ctypes.c_uint64(0)
+    rc = lib().radic_host_binomial(int(a), int(b), ctypes.byref(out))
+    _check(rc, "radic_host_binomial")
+    return int(out.value)
+
+
+def host_unrank(m, n, q):
+    cols = (ctypes.c_int * m)()
+    _check(lib().radic_host_unrank(int(m), int(n), int(q), cols), "radic_host_unrank")
+    return list(cols)
+
+
+def host_prime(i):
+    p = ctypes.c_uint32(0)
+    _check(lib().radic_host_prime(int(i), ctypes.byref(p)), "radic_host_prime")
+    return int(p.value)

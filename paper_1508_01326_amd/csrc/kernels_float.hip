@@ -1,0 +1,561 @@
+// Floating-point Radic determinant kernels for gfx950.
+//
+// One lane owns a chunk of `spl` consecutive dictionary ranks (the granularity
+// scheme of Section 5).  Consecutive lanes of a wave own consecutive chunks, so
+// the 64 minors a wave factors at any moment lie in a short stretch of the
+// dictionary order and share their leading columns; the pivot row of the first
+// LU steps is then usually the same in every lane, and row exchanges are done by
+// a scalar branch over the distinct pivot rows present in the wave ("waterfall")
+// instead of per-lane select chains.  Per subset a lane:
+//   1. holds its ascending sequence as M column indices (unranked once per chunk
+//      with the combinatorial addition of Section 4, then advanced with the
+//      dictionary successor of Section 5);
+//   2. gathers the M columns of the minor from LDS, where the workgroup staged A
+//      column-major once (the EREW replication of A in Section 6 becomes one
+//      staging per workgroup);
+//   3. factors the minor by LU with partial pivoting in registers;
+//   4. applies (-1)^(r+s) and the row-exchange parity (Definition 3, eq. (1));
+//   5. accumulates the signed term with TwoSum into a double-double and |det|.
+// Partials are combined wave -> workgroup -> grid in a fixed order (the tree sum
+// of Section 6), so results are bitwise reproducible for a given launch shape.
+#include <type_traits>
+
+#include "radic_internal.h"
+
+namespace radic {
+
+// Binomial coefficients C(x, y), x < kBinomRows, y < kBinomCols, saturated at
+// 2^64-1; filled once per device by the host.
+constexpr int kBinomRows = RADIC_MAX_N + 1;
+constexpr int kBinomCols = 16;
+__device__ unsigned long long g_binom[kBinomRows * kBinomCols];
+
+// ---------------------------------------------------------------- LDS layout
+// Columns are stored contiguously with a stride (in 16-byte groups) chosen odd so
+// that lanes reading different columns start on different bank groups.
+template <int M> struct Layout {
+    static constexpr int g64 = (((M + 1) / 2) % 2 == 0) ? (M + 1) / 2 + 1 : (M + 1) / 2;
+    static constexpr int st64 = 2 * g64;                  // doubles per column
+    static constexpr int g32 = (((M + 4) / 4) % 2 == 0) ? (M + 4) / 4 + 1 : (M + 4) / 4;
+    static constexpr int st32 = 4 * g32;                  // floats per column (+1 slot: column scale)
+};
+
+__host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
+
+template <int M> __host__ __device__ constexpr int binom_bytes(int n) { return align16(n * M * 8); }
+
+// Per-wave fallback region: queue of 16-byte entries + M x M double scratch.
+template <int M> __host__ __device__ constexpr int fallback_wave_bytes() {
+    return kFallbackCap * 16 + align16(M * M * 8);
+}
+
+template <int M, bool F32> __host__ __device__ int lds_bytes(int n, int waves) {
+    int b = binom_bytes<M>(n) + align16(n * Layout<M>::st64 * 8);
+    if (F32) b += align16(n * Layout<M>::st32 * 4) + waves * fallback_wave_bytes<M>();
+    return b;
+}
+
+// ---------------------------------------------------------------- staging
+template <int M>
+__device__ void stage_binomials(unsigned long long* bt, int n) {
+    for (int e = threadIdx.x; e < n * M; e += blockDim.x) {
+        int x = e / M, y = e - x * M;
+        bt[e] = g_binom[x * kBinomCols + y];
+    }
+}
+
+// Stage A column-major into LDS (double copy; for F32 also the row-scaled float
+// copy and the per-column scale).  Returns the workgroup-wide non-finite flag.
+template <int M, bool F32>
+__device__ int stage_matrix(const FloatJob& J, double* cd, float* cf, int* rowexp) {
+    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    const int n = J.n;
+    int bad = 0;
+    if (F32) {
+        // e_i: exponent of the row maximum, max|a_ij| = f 2^e_i with f in [0.5, 1)
+        if (threadIdx.x < M) {
+            const double* row = J.A + (long long)threadIdx.x * J.lda;
+            double mx = 0.0;
+            for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(row[j]));
+            int e = 0;
+            if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+            rowexp[threadIdx.x] = e;
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < M * n; e += blockDim.x) {
+        int i = e / n, j = e - i * n;
+        double v = J.A[(long long)i * J.lda + j];
+        bad |= !isfinite(v);
+        if (F32) v = ldexp(v, -rowexp[i]);   // exact power-of-two scaling
+        cd[j * ST64 + i] = v;
+        if (F32) cf[j * ST32 + i] = (float)v;
+    }
+    bad = __syncthreads_or(bad);
+    if (F32) {
+        for (int j = threadIdx.x; j < n; j += blockDim.x) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < M; ++i) s = fmaxf(s, fabsf(cf[j * ST32 + i]));
+            cf[j * ST32 + M] = s;
+        }
+        __syncthreads();
+    }
+    return bad;
+}
+
+// ---------------------------------------------------------------- sequences
+// Dictionary-order unranking (Section 4): at place k the sequences that put the
+// value c there number C(n-1-c, M-1-k) (0-based c); step c to the right while q
+// can pay for them.  bt[x*M + y] = C(x, y).
+template <int M>
+__device__ __forceinline__ void unrank(unsigned long long q, int n, const unsigned long long* bt, int (&col)[M]) {
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        for (;;) {
+            unsigned long long w = bt[(n - 1 - c) * M + (M - 1 - k)];
+            if (q < w) break;
+            q -= w;
+            ++c;
+        }
+        col[k] = c;
+        ++c;
+    }
+}
+
+// Dictionary successor (Section 5): the rightmost place still below its maximum
+// n-M+j moves up by one and the places after it follow consecutively.  Written
+// without branches; from the last member it wraps to the first (callers never
+// use that value).
+template <int M>
+__device__ __forceinline__ void successor(int (&col)[M], int n) {
+    int ip = -1, t = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        bool nf = col[j] < n - M + j;
+        ip = nf ? j : ip;
+        t = nf ? col[j] - j + 1 : t;
+    }
+#pragma unroll
+    for (int j = 0; j < M; ++j) col[j] = (j >= ip) ? t + j : col[j];
+}
+
+// Parity of r + s in (-1)^(r+s): r = M(M+1)/2, s = sum of 1-based columns.
+template <int M>
+__device__ __forceinline__ bool radic_sign_odd(const int (&col)[M]) {
+    int s = M * (M + 1) / 2 + M;
+#pragma unroll
+    for (int j = 0; j < M; ++j) s += col[j];
+    return s & 1;
+}
+
+// ---------------------------------------------------------------- LU building blocks
+template <int M, typename T>
+__device__ __forceinline__ void gather(T (&a)[M][M], const T* base, int stride, const int (&col)[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const T* src = base + col[j] * stride;
+        if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int i = 0; i + 1 < M; i += 2) {
+                double2 v = *reinterpret_cast<const double2*>(src + i);
+                a[i][j] = v.x;
+                a[i + 1][j] = v.y;
+            }
+            if (M & 1) a[M - 1][j] = src[M - 1];
+        } else {
+#pragma unroll
+            for (int i = 0; i + 3 < M; i += 4) {
+                float4 v = *reinterpret_cast<const float4*>(src + i);
+                a[i][j] = v.x;
+                a[i + 1][j] = v.y;
+                a[i + 2][j] = v.z;
+                a[i + 3][j] = v.w;
+            }
+#pragma unroll
+            for (int i = (M / 4) * 4; i < M; ++i) a[i][j] = src[i];
+        }
+    }
+}
+
+// Bring each lane's pivot row p into row K with selects.  Only candidate rows
+// that some lane of the wave chose are visited (a wave-uniform test), so a step
+// on which the whole wave keeps row K costs one ballot.
+template <int M, int K, typename T>
+__device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p) {
+#pragma unroll
+    for (int i = K + 1; i < M; ++i) {
+        const bool c = (p == i);
+        if (__ballot(c)) {
+#pragma unroll
+            for (int j = K; j < M; ++j) {
+                const T x = a[K][j], y = a[i][j];
+                a[K][j] = c ? y : x;
+                a[i][j] = c ? x : y;
+            }
+        }
+    }
+}
+
+// LU with partial pivoting of the register-resident minor, one step per
+// template level K so that every register index is a compile-time constant.
+// Accumulates the pivots into det, raises `zero` for an exactly zero pivot
+// column, flips `neg` once per row exchange and, for FP32 (CHECK), raises `flag`
+// when a pivot falls below tau * s_k.
+template <int M, int K, typename T, bool CHECK>
+__device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool& neg, bool& flag,
+                                         const T (&s)[M], T tau) {
+    if constexpr (K < M - 1) {
+        unsigned best = pivot_key(a[K][K], K);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(a[i][K], i));
+        const int p = pivot_row(best);
+        neg ^= (p != K);
+        exchange_rows<M, K, T>(a, p);
+        const T piv = a[K][K];
+        zero |= (piv == T(0));
+        if (CHECK) flag |= !(__builtin_fabsf((float)piv) >= (float)(tau * s[K]));
+        det *= piv;
+        const T r = recip(piv);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) {
+            const T l = a[i][K] * r;
+#pragma unroll
+            for (int j = K + 1; j < M; ++j) a[i][j] = __builtin_fma(-l, a[K][j], a[i][j]);
+        }
+        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, flag, s, tau);
+    }
+}
+
+// Determinant of the minor (0 for an exactly zero pivot column).
+template <int M, typename T, bool CHECK>
+__device__ __forceinline__ T lu_det(T (&a)[M][M], bool& neg, bool& flag, const T (&s)[M], T tau) {
+    T det = T(1);
+    bool zero = false;
+    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, flag, s, tau);
+    const T last = a[M - 1][M - 1];
+    if (CHECK) flag |= !(__builtin_fabsf((float)last) >= (float)(tau * s[M - 1]));
+    det *= last;
+    return zero ? T(0) : det;
+}
+
+// ---------------------------------------------------------------- FP64 refactorisation (wave-cooperative)
+// One minor at a time, factored by the whole wave in LDS: exact first-maximum
+// partial pivoting and true division, as in the textbook algorithm.
+template <int M>
+__device__ double coop_det_f64(const double* cd, const int (&c)[M], double* W, int lane) {
+    constexpr int ST64 = Layout<M>::st64;
+    for (int t = lane; t < M * M; t += kWave) {
+        int i = t / M, j = t - i * M;
+        W[t] = cd[c[j] * ST64 + i];
+    }
+    wave_lds_sync();
+    double det = 1.0;
+    bool neg = false, zero = false;
+    for (int k = 0; k < M; ++k) {
+        double v = (lane >= k && lane < M) ? fabs(W[lane * M + k]) : -1.0;
+        if (v != v) v = __builtin_inf();   // a NaN entry is taken as the largest
+        int idx = lane;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            double v2 = shfl_xor_d(v, off);
+            int i2 = __shfl_xor(idx, off, kWave);
+            if (v2 > v || (v2 == v && i2 < idx)) { v = v2; idx = i2; }
+        }
+        if (v == 0.0) { zero = true; break; }
+        const int p = (idx >= k && idx < M) ? idx : k;
+        if (p != k) {
+            neg = !neg;
+            if (lane >= k && lane < M) {
+                double x = W[k * M + lane];
+                W[k * M + lane] = W[p * M + lane];
+                W[p * M + lane] = x;
+            }
+        }
+        wave_lds_sync();
+        const double piv = W[k * M + k];
+        det *= piv;
+        const int w = M - 1 - k;
+        for (int t = lane; t < w * w; t += kWave) {
+            int i = k + 1 + t / w, j = k + 1 + t % w;
+            double l = W[i * M + k] / piv;
+            W[i * M + j] -= l * W[k * M + j];
+        }
+        wave_lds_sync();
+    }
+    return zero ? 0.0 : (neg ? -det : det);
+}
+
+template <int M>
+__device__ __forceinline__ void pack_cols(const int (&col)[M], unsigned (&w)[3]) {
+    w[0] = w[1] = w[2] = 0u;
+#pragma unroll
+    for (int j = 0; j < M; ++j) w[j / 4] |= (unsigned)col[j] << (8 * (j % 4));
+}
+
+template <int M>
+__device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) col[j] = (w[j / 4] >> (8 * (j % 4))) & 0xFF;
+}
+
+// Refactor every queued minor in double; lane 0 accumulates the terms.
+template <int M, bool EXPORT>
+__device__ void flush_fallback(const FloatJob& J, const double* cd, unsigned* queue, int count, double* W,
+                               int lane, double& hi, double& lo, double& ab) {
+    for (int e = 0; e < count; ++e) {
+        int c[M];
+        unpack_cols<M>(queue + 4 * e, c);
+        const unsigned off = queue[4 * e + 3];
+        double d = coop_det_f64<M>(cd, c, W, lane);
+        const double term = radic_sign_odd<M>(c) ? -d : d;
+        if (lane == 0) {
+            double s, err;
+            two_sum(hi, term, s, err);
+            hi = s;
+            lo += err;
+            ab += fabs(d);
+            if (EXPORT) J.terms[off] = term;
+        }
+        wave_lds_sync();
+    }
+}
+
+// ---------------------------------------------------------------- main kernel
+template <int M, bool F32, bool EXPORT>
+__global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
+    using T = typename std::conditional<F32, float, double>::type;
+    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int rowexp[RADIC_MAX_M];
+    __shared__ double red[4 * 16];
+    __shared__ unsigned long long redn[16];
+
+    const int n = J.n;
+    const int waves = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+
+    unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
+    double* cd = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
+    float* cf = reinterpret_cast<float*>(smem + binom_bytes<M>(n) + align16(n * ST64 * 8));
+    unsigned char* fb = smem + binom_bytes<M>(n) + align16(n * ST64 * 8) + align16(n * ST32 * 4) +
+                        wave * fallback_wave_bytes<M>();
+    unsigned* queue = reinterpret_cast<unsigned*>(fb);
+    double* W = reinterpret_cast<double*>(fb + kFallbackCap * 16);
+
+    stage_binomials<M>(bt, n);
+    const int bad = stage_matrix<M, F32>(J, cd, cf, rowexp);
+    if (!EXPORT && blockIdx.x == 0 && threadIdx.x == 0) {
+        J.header->nonfinite = bad;
+        int se = 0;
+        if (F32)
+            for (int i = 0; i < M; ++i) se += rowexp[i];
+        J.header->scale_exp = se;
+    }
+
+    double hi = 0.0, lo = 0.0, ab = 0.0;
+    unsigned long long nfb = 0;
+    int qcount = 0;   // wave-uniform fallback queue length
+    const T* colbase = F32 ? reinterpret_cast<const T*>(cf) : reinterpret_cast<const T*>(cd);
+    const int colstride = F32 ? ST32 : ST64;
+    const T tau = (T)J.tau;
+
+    const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
+    const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
+    for (unsigned long long wc = gwave * kWave; wc < J.chunks; wc += nwaves * kWave) {
+        const unsigned long long chunk = wc + lane;
+        const bool vchunk = chunk < J.chunks;
+        const unsigned long long off0 = vchunk ? chunk * (unsigned long long)J.spl : J.count - 1;
+        const unsigned long long left = J.count - off0;
+        const int cnt = vchunk ? (int)(left < (unsigned long long)J.spl ? left : (unsigned long long)J.spl) : 0;
+        int col[M];
+        unrank<M>(J.q_begin + off0, n, bt, col);
+        for (int s = 0; s < J.spl; ++s) {
+            const bool valid = s < cnt;
+            T a[M][M];
+            gather<M, T>(a, colbase, colstride, col);
+            T sc[M];
+            if (F32) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) sc[j] = colbase[col[j] * colstride + M];
+            }
+            bool neg = radic_sign_odd<M>(col);
+            bool flag = false;
+            const T det = lu_det<M, T, F32>(a, neg, flag, sc, tau);
+            flag = flag && valid;
+            if (valid && !flag) {
+                const double d = (double)det;
+                const double term = neg ? -d : d;
+                double sum, err;
+                two_sum(hi, term, sum, err);
+                hi = sum;
+                lo += err;
+                ab += fabs(d);
+                if (EXPORT) {
+                    J.terms[off0 + s] = term;
+                }
+            }
+            if (EXPORT && valid && J.cols) {
+#pragma unroll
+                for (int j = 0; j < M; ++j) J.cols[(off0 + s) * M + j] = (unsigned char)(col[j] + 1);
+            }
+            if (F32) {
+                const unsigned long long fm = __ballot(flag);
+                if (fm) {
+                    if (flag) {
+                        const int pos = qcount + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+                        unsigned w[3];
+                        pack_cols<M>(col, w);
+                        queue[4 * pos + 0] = w[0];
+                        queue[4 * pos + 1] = w[1];
+                        queue[4 * pos + 2] = w[2];
+                        queue[4 * pos + 3] = (unsigned)(off0 + s);
+                        nfb += 1;
+                    }
+                    qcount += __popcll(fm);
+                    if (qcount > kFallbackCap - kWave) {
+                        wave_lds_sync();
+                        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab);
+                        qcount = 0;
+                    }
+                }
+            }
+            successor<M>(col, n);
+        }
+    }
+    if (F32 && qcount > 0) {
+        wave_lds_sync();
+        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab);
+    }
+    if (EXPORT) return;
+
+    wave_reduce_partial(hi, lo, ab, nfb);
+    if (lane == 0) {
+        red[4 * wave + 0] = hi;
+        red[4 * wave + 1] = lo;
+        red[4 * wave + 2] = ab;
+        redn[wave] = nfb;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double h = red[0], l = red[1], a2 = red[2];
+        unsigned long long nf = redn[0];
+        for (int w = 1; w < waves; ++w) {
+            dd_add(h, l, red[4 * w + 0], red[4 * w + 1]);
+            a2 += red[4 * w + 2];
+            nf += redn[w];
+        }
+        J.partials[blockIdx.x] = Partial{h, l, a2, nf};
+    }
+}
+
+// Fixed-order reduction of the workgroup partials into the result record.
+__global__ __launch_bounds__(256) void k_finalize_float(const Partial* parts, int G, const DetHeader* h,
+                                                        radic_f64_result* out, unsigned long long count,
+                                                        int use_scale) {
+    __shared__ double sh[256], sl[256], sa[256];
+    __shared__ unsigned long long sn[256];
+    double hi = 0.0, lo = 0.0, ab = 0.0;
+    unsigned long long nf = 0;
+    for (int i = threadIdx.x; i < G; i += blockDim.x) {
+        Partial p = parts[i];
+        dd_add(hi, lo, p.hi, p.lo);
+        ab += p.abs;
+        nf += p.nfb;
+    }
+    sh[threadIdx.x] = hi;
+    sl[threadIdx.x] = lo;
+    sa[threadIdx.x] = ab;
+    sn[threadIdx.x] = nf;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            double a = sh[threadIdx.x], b = sl[threadIdx.x];
+            dd_add(a, b, sh[threadIdx.x + w], sl[threadIdx.x + w]);
+            sh[threadIdx.x] = a;
+            sl[threadIdx.x] = b;
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sn[threadIdx.x] += sn[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int e = use_scale ? h->scale_exp : 0;
+        radic_f64_result r;
+        r.hi = ldexp(sh[0], e);
+        r.lo = ldexp(sl[0], e);
+        r.abs_sum = ldexp(sa[0], e);
+        r.value = r.hi + r.lo;
+        r.n_subsets = count;
+        r.n_fallback = sn[0];
+        r.status = h->nonfinite ? RADIC_ENONFINITE : RADIC_OK;
+        r.reserved = 0;
+        if (h->nonfinite) r.value = __builtin_nan("");
+        *out = r;
+    }
+}
+
+__global__ void k_write_zero_result(radic_f64_result* out) {
+    radic_f64_result r{};
+    r.status = RADIC_OK;
+    *out = r;
+}
+
+// ---------------------------------------------------------------- host launchers
+template <int M, bool F32, bool EXPORT>
+static hipError_t launch_m(const FloatJob& J, int grid, int block, hipStream_t s) {
+    const int lds = lds_bytes<M, F32>(J.n, block / kWave);
+    hipLaunchKernelGGL((k_radic_float<M, F32, EXPORT>), dim3(grid), dim3(block), lds, s, J);
+    return hipGetLastError();
+}
+
+template <bool F32, bool EXPORT>
+static hipError_t launch_dispatch(int m, const FloatJob& J, int grid, int block, hipStream_t s) {
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: return launch_m<MM, F32, EXPORT>(J, grid, block, s);
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
+#undef RADIC_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int float_lds_bytes(int m, int n, int prec, int waves) {
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: return prec == RADIC_FP32_BULK ? lds_bytes<MM, true>(n, waves) : lds_bytes<MM, false>(n, waves);
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
+#undef RADIC_CASE
+        default: return 1 << 30;
+    }
+}
+
+hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, int grid, int block, hipStream_t s) {
+    if (prec == RADIC_FP32_BULK)
+        return export_terms ? launch_dispatch<true, true>(m, J, grid, block, s)
+                            : launch_dispatch<true, false>(m, J, grid, block, s);
+    return export_terms ? launch_dispatch<false, true>(m, J, grid, block, s)
+                        : launch_dispatch<false, false>(m, J, grid, block, s);
+}
+
+hipError_t launch_finalize_float(const Partial* parts, int G, const DetHeader* h, radic_f64_result* out,
+                                 unsigned long long count, int use_scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(256), 0, s, parts, G, h, out, count, use_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_write_zero_result, dim3(1), dim3(1), 0, s, out);
+    return hipGetLastError();
+}
+
+hipError_t upload_binomials(const unsigned long long* host_table) {
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_binom), host_table, sizeof(unsigned long long) * kBinomRows * kBinomCols);
+}
+
+}  // namespace radic

@@ -1,0 +1,393 @@
+// C ABI of the Radic library: argument validation, workspace layout, launch-shape
+// selection and dispatch to the HIP kernels.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "radic_internal.h"
+
+namespace radic {
+
+hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, int grid, int block, hipStream_t s);
+hipError_t launch_finalize_float(const Partial* parts, int G, const DetHeader* h, radic_f64_result* out,
+                                 unsigned long long count, int use_scale, hipStream_t s);
+hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s);
+hipError_t upload_binomials(const unsigned long long* host_table);
+int float_lds_bytes(int m, int n, int prec, int waves);
+
+constexpr int kBinomRows = RADIC_MAX_N + 1;
+constexpr int kBinomCols = 16;
+constexpr size_t kHeaderBytes = 256;
+constexpr int kMaxLds = 64 * 1024;
+constexpr unsigned long long kRankLimit = 1ull << 63;
+
+// ---------------------------------------------------------------- binomials
+int host_binomial(int a, int b, unsigned long long* out) {
+    *out = 0;
+    if (a < 0 || b < 0 || b > a) return RADIC_OK;
+    if (b > a - b) b = a - b;
+    unsigned __int128 v = 1;
+    for (int i = 1; i <= b; ++i) {
+        v = v * (unsigned __int128)(a - b + i) / (unsigned __int128)i;   // exact at every step
+        if (v > (unsigned __int128)~0ull) return RADIC_EOVERFLOW;
+    }
+    *out = (unsigned long long)v;
+    return RADIC_OK;
+}
+
+// ---------------------------------------------------------------- per-device state
+static std::mutex g_mu;
+static bool g_dev_ready[64];
+
+static int ensure_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RADIC_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (g_dev_ready[dev]) return RADIC_OK;
+    std::vector<unsigned long long> t((size_t)kBinomRows * kBinomCols, 0);
+    for (int x = 0; x < kBinomRows; ++x)
+        for (int y = 0; y < kBinomCols; ++y) {
+            unsigned long long v = 0;
+            if (host_binomial(x, y, &v) != RADIC_OK) v = ~0ull;   // saturate; never used
+            t[(size_t)x * kBinomCols + y] = v;
+        }
+    if (upload_binomials(t.data()) != hipSuccess) return RADIC_EDEVICE;
+    g_dev_ready[dev] = true;
+    return RADIC_OK;
+}
+
+// ---------------------------------------------------------------- launch shapes
+struct Shape {
+    int spl;
+    int block;
+};
+static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;   // (kind, prec, m, n) -> shape
+static int g_force_spl = 0, g_force_block = 0;
+static double g_tau = 1.0 / 1024.0;
+
+static Shape default_shape(int kind, int prec, int m, int n) {
+    (void)kind;
+    (void)prec;
+    (void)n;
+    Shape s{8, 256};
+    if (m <= 3) s.spl = 32;
+    return s;
+}
+
+static Shape pick_shape(int kind, int prec, int m, int n) {
+    Shape s = default_shape(kind, prec, m, n);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_tuned.find(std::make_tuple(kind, prec, m, n));
+        if (it != g_tuned.end()) s = it->second;
+        if (g_force_spl > 0) s.spl = g_force_spl;
+        if (g_force_block > 0) s.block = g_force_block;
+    }
+    return s;
+}
+
+// ---------------------------------------------------------------- profiling hook
+static bool g_prof = false;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_prof_events;
+static std::vector<hipEvent_t> g_event_pool;
+
+static hipEvent_t take_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct ProfScope {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipStream_t s;
+    explicit ProfScope(hipStream_t st) : s(st) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_prof) return;
+        a = take_event();
+        b = take_event();
+        if (a) hipEventRecord(a, s);
+    }
+    ~ProfScope() {
+        if (!a || !b) return;
+        hipEventRecord(b, s);
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_prof_events.emplace_back(a, b);
+    }
+};
+
+// ---------------------------------------------------------------- validation helpers
+static int check_workspace(void* ws, size_t bytes, size_t need) {
+    if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || bytes < need) return RADIC_EWORKSPACE;
+    return RADIC_OK;
+}
+
+static size_t det_workspace_bytes() { return kHeaderBytes + sizeof(Partial) * (size_t)kMaxGrid; }
+
+static int float_common_checks(const double* dA, int m, int n, long long lda, int prec) {
+    if (!dA || m < 1 || n < 1 || lda < n) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (m > n) return RADIC_OK;
+    if (m > RADIC_MAX_M || n > RADIC_MAX_N) return RADIC_ENOTSUP;
+    return RADIC_OK;
+}
+
+static int grid_for(unsigned long long chunks, int block) {
+    const unsigned long long wave_chunks = (chunks + kWave - 1) / kWave;
+    const unsigned long long wpb = (unsigned long long)(block / kWave);
+    unsigned long long g = (wave_chunks + wpb - 1) / wpb;
+    if (g > (unsigned long long)kMaxGrid) g = kMaxGrid;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+static int det_range_impl(const double* dA, int m, int n, long long lda, int prec, unsigned long long q_begin,
+                          unsigned long long count, bool whole, radic_f64_result* dOut, void* dWork,
+                          size_t work_bytes, hipStream_t stream) {
+    if (!dOut) return RADIC_EINVAL;
+    int rc = float_common_checks(dA, m, n, lda, prec);
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    if (m > n) return launch_zero_result(dOut, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
+    if ((rc = check_workspace(dWork, work_bytes, det_workspace_bytes())) != RADIC_OK) return rc;
+    if (whole) {
+        q_begin = 0;
+        count = total;
+    } else {
+        if (q_begin >= total) count = 0;
+        else if (count > total - q_begin) count = total - q_begin;
+    }
+    if (count == 0) return launch_zero_result(dOut, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
+    if (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) return RADIC_ENOTSUP;
+
+    unsigned char* ws = static_cast<unsigned char*>(dWork);
+    FloatJob J{};
+    J.A = dA;
+    J.lda = lda;
+    J.m = m;
+    J.n = n;
+    J.q_begin = q_begin;
+    J.count = count;
+    J.spl = sh.spl;
+    J.chunks = (count + sh.spl - 1) / sh.spl;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        J.tau = g_tau;
+    }
+    J.header = reinterpret_cast<DetHeader*>(ws);
+    J.partials = reinterpret_cast<Partial*>(ws + kHeaderBytes);
+    const int grid = grid_for(J.chunks, sh.block);
+    hipError_t e;
+    {
+        ProfScope ps(stream);
+        e = launch_float(m, prec, false, J, grid, sh.block, stream);
+    }
+    if (e != hipSuccess) return RADIC_EDEVICE;
+    e = launch_finalize_float(J.partials, grid, J.header, dOut, count, prec == RADIC_FP32_BULK, stream);
+    return e == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+}
+
+}  // namespace radic
+
+using namespace radic;
+
+extern "C" {
+
+const char* radic_status_string(int status) {
+    switch (status) {
+        case RADIC_OK: return "RADIC_OK";
+        case RADIC_EINVAL: return "RADIC_EINVAL: invalid argument";
+        case RADIC_ENOTSUP: return "RADIC_ENOTSUP: shape not supported";
+        case RADIC_EOVERFLOW: return "RADIC_EOVERFLOW: count or result does not fit";
+        case RADIC_ENOMEM: return "RADIC_ENOMEM: host allocation failed";
+        case RADIC_EDEVICE: return "RADIC_EDEVICE: HIP call failed";
+        case RADIC_EWORKSPACE: return "RADIC_EWORKSPACE: workspace missing, misaligned or too small";
+        case RADIC_ENONFINITE: return "RADIC_ENONFINITE: non-finite input";
+        default: return "unknown radic status";
+    }
+}
+
+int radic_version(void) { return 100; }
+
+size_t radic_workspace_bytes(int kind, int m, int n, int batch) {
+    switch (kind) {
+        case RADIC_WS_DET:
+            if (m < 1 || n < 1) return 0;
+            return det_workspace_bytes();
+        default:
+            (void)batch;
+            return 0;
+    }
+}
+
+int radic_det(const double* dA, int m, int n, int64_t lda, int prec, radic_f64_result* dOut, void* dWork,
+              size_t work_bytes, hipStream_t stream) {
+    return det_range_impl(dA, m, n, lda, prec, 0, 0, true, dOut, dWork, work_bytes, stream);
+}
+
+int radic_det_range(const double* dA, int m, int n, int64_t lda, int prec, uint64_t q_begin, uint64_t count,
+                    radic_f64_result* dOut, void* dWork, size_t work_bytes, hipStream_t stream) {
+    return det_range_impl(dA, m, n, lda, prec, q_begin, count, false, dOut, dWork, work_bytes, stream);
+}
+
+int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uint64_t q_begin, uint64_t count,
+                      double* dTerms, uint8_t* dCols, hipStream_t stream) {
+    if (!dTerms) return RADIC_EINVAL;
+    int rc = float_common_checks(dA, m, n, lda, prec);
+    if (rc != RADIC_OK) return rc;
+    if (m > n) return RADIC_EINVAL;   // no terms exist
+    if (dCols && n > 255) return RADIC_ENOTSUP;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
+    if (q_begin >= total || count == 0) return RADIC_OK;
+    if (count > total - q_begin) count = total - q_begin;
+    if (count > (1ull << 31)) return RADIC_EOVERFLOW;
+    Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
+    if (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) return RADIC_ENOTSUP;
+    FloatJob J{};
+    J.A = dA;
+    J.lda = lda;
+    J.m = m;
+    J.n = n;
+    J.q_begin = q_begin;
+    J.count = count;
+    J.spl = sh.spl;
+    J.chunks = (count + sh.spl - 1) / sh.spl;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        J.tau = g_tau;
+    }
+    J.terms = dTerms;
+    J.cols = dCols;
+    const int grid = grid_for(J.chunks, sh.block);
+    return launch_float(m, prec, true, J, grid, sh.block, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+}
+
+int radic_det_int_exact(const int32_t*, int, int, int64_t, uint32_t*, int, int*, int*, void*, size_t, hipStream_t) {
+    return RADIC_ENOTSUP;
+}
+
+int radic_det_batched(const radic_matrix_desc*, int, const double*, const int32_t*, int, radic_batch_result*,
+                      void*, size_t, hipStream_t) {
+    return RADIC_ENOTSUP;
+}
+
+int radic_batched_graph_create(const radic_matrix_desc*, int, const double*, const int32_t*, int,
+                               radic_batch_result*, void*, size_t, void**) {
+    return RADIC_ENOTSUP;
+}
+int radic_graph_launch(void*, hipStream_t) { return RADIC_ENOTSUP; }
+int radic_graph_destroy(void*) { return RADIC_ENOTSUP; }
+
+int radic_autotune(int, int, int, int, int*, hipStream_t) { return RADIC_ENOTSUP; }
+int radic_tune_save(const char*) { return RADIC_ENOTSUP; }
+int radic_tune_load(const char*) { return RADIC_ENOTSUP; }
+
+int radic_set_launch(int subsets_per_lane, int block_size) {
+    if (subsets_per_lane < 0 || subsets_per_lane > 4096) return RADIC_EINVAL;
+    if (block_size != 0 && (block_size < 64 || block_size > 1024 || block_size % 64)) return RADIC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_spl = subsets_per_lane;
+    g_force_block = block_size;
+    return RADIC_OK;
+}
+
+int radic_set_fallback_tau(double tau) {
+    if (std::isnan(tau) || tau < 0) return RADIC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_tau = tau;
+    return RADIC_OK;
+}
+
+int radic_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_prof = on != 0;
+    return RADIC_OK;
+}
+
+static int profile_collect(std::vector<double>& ms_out) {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ev.swap(g_prof_events);
+    }
+    int rc = RADIC_OK;
+    for (auto& p : ev) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second) != hipSuccess || hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            rc = RADIC_EDEVICE;
+        ms_out.push_back(ms);
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto& p : ev) {
+        g_event_pool.push_back(p.first);
+        g_event_pool.push_back(p.second);
+    }
+    return rc;
+}
+
+int radic_profile_read(double* hTotalMs, int* hLaunches) {
+    if (!hTotalMs || !hLaunches) return RADIC_EINVAL;
+    std::vector<double> ms;
+    int rc = profile_collect(ms);
+    double total = 0.0;
+    for (double v : ms) total += v;
+    *hTotalMs = total;
+    *hLaunches = (int)ms.size();
+    return rc;
+}
+
+int radic_profile_read_launches(double* hMs, int capacity, int* hCount) {
+    if (!hCount || capacity < 0 || (capacity > 0 && !hMs)) return RADIC_EINVAL;
+    std::vector<double> ms;
+    int rc = profile_collect(ms);
+    for (int i = 0; i < (int)ms.size() && i < capacity; ++i) hMs[i] = ms[i];
+    *hCount = (int)ms.size();
+    return rc;
+}
+
+int radic_host_binomial(int a, int b, uint64_t* hOut) {
+    if (!hOut || a < 0 || b < 0) return RADIC_EINVAL;
+    unsigned long long v = 0;
+    int rc = host_binomial(a, b, &v);
+    *hOut = v;
+    return rc;
+}
+
+int radic_host_unrank(int m, int n, uint64_t q, int* hCols) {
+    if (!hCols || m < 1 || n < m || m > 64) return RADIC_EINVAL;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK) return RADIC_EOVERFLOW;
+    if (q >= total) return RADIC_EINVAL;
+    int c = 0;
+    for (int k = 0; k < m; ++k) {
+        for (;;) {
+            unsigned long long w = 0;
+            host_binomial(n - 1 - c, m - 1 - k, &w);
+            if (q < w) break;
+            q -= w;
+            ++c;
+        }
+        hCols[k] = c + 1;
+        ++c;
+    }
+    return RADIC_OK;
+}
+
+int radic_host_prime(int, uint32_t*) { return RADIC_ENOTSUP; }
+
+}  // extern "C"

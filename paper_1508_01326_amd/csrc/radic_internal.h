@@ -1,0 +1,123 @@
+// Internal definitions shared by the HIP translation units of the Radic library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "radic.h"
+
+namespace radic {
+
+constexpr int kWave = 64;            // CDNA4 wavefront width
+constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
+constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
+constexpr int kBatchChunksPerMatrix = 256;
+
+// Per-workgroup partial of a floating-point enumeration (32 bytes).
+struct Partial {
+    double hi;
+    double lo;
+    double abs;
+    unsigned long long nfb;
+};
+
+// Header at the start of a single-matrix workspace.
+struct DetHeader {
+    int nonfinite;     // set by workgroup 0 while staging A
+    int scale_exp;     // FP32_BULK: sum of the row exponents e_i
+    int n_primes;      // exact path: primes used
+    int pad;
+    double bound_log2; // exact path: log2 of the bound on |result|
+};
+
+// Launch description of one single-matrix float enumeration.
+struct FloatJob {
+    const double* A;
+    long long lda;
+    int m, n;
+    unsigned long long q_begin;   // first dictionary rank
+    unsigned long long count;     // ranks to evaluate
+    unsigned long long chunks;    // ceil(count / spl)
+    int spl;                      // ranks per lane chunk ("subsets per lane")
+    double tau;                   // FP32_BULK fallback threshold
+    Partial* partials;            // [gridDim.x], unless exporting
+    DetHeader* header;
+    double* terms;                // export mode: [count]
+    unsigned char* cols;          // export mode: [count * m] or null
+};
+
+// ---------------------------------------------------------------- arithmetic helpers
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) += (h2, l2), renormalised so that |lo| <= ulp(hi)/2.
+__device__ __forceinline__ void dd_add(double& hi, double& lo, double h2, double l2) {
+    double s, e;
+    two_sum(hi, h2, s, e);
+    e += lo + l2;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int mask) {
+    return __shfl_xor(v, mask, kWave);
+}
+
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int mask) {
+    return __shfl_xor(v, mask, kWave);
+}
+
+// Compiler-level ordering of LDS traffic issued by a single wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Wave-wide combination of lane partials in a fixed butterfly order.
+__device__ __forceinline__ void wave_reduce_partial(double& hi, double& lo, double& ab, unsigned long long& nfb) {
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        double h2 = shfl_xor_d(hi, off);
+        double l2 = shfl_xor_d(lo, off);
+        double a2 = shfl_xor_d(ab, off);
+        unsigned long long n2 = shfl_xor_u64(nfb, off);
+        dd_add(hi, lo, h2, l2);
+        ab += a2;
+        nfb += n2;
+    }
+}
+
+// Pivot key: the magnitude's leading bits with the row index in the low 4 bits,
+// arranged so that an unsigned max picks the largest magnitude and, among
+// magnitudes equal in the kept bits, the lowest row.  For double the kept bits
+// are the exponent and 16 mantissa bits (the high word with sign and the four
+// lowest bits cleared); for float the exponent and 19 mantissa bits.
+__device__ __forceinline__ unsigned pivot_key(double x, int row) {
+    unsigned hi = (unsigned)__double2hiint(x);
+    return (hi & 0x7FFFFFF0u) | (unsigned)(15 - row);
+}
+__device__ __forceinline__ unsigned pivot_key(float x, int row) {
+    unsigned b = (unsigned)__float_as_int(x);
+    return (b & 0x7FFFFFF0u) | (unsigned)(15 - row);
+}
+__device__ __forceinline__ int pivot_row(unsigned key) { return 15 - (int)(key & 15u); }
+
+// Reciprocal for the elimination multipliers: hardware estimate refined by two
+// Newton-Raphson steps (double) or used as is (float, where its error is below
+// the float rounding of the products it feeds).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ---------------------------------------------------------------- host helpers
+int host_binomial(int a, int b, unsigned long long* out);   // 0 or RADIC_EOVERFLOW
+
+}  // namespace radic

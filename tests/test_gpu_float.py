@@ -1,0 +1,225 @@
+"""GPU parity of the floating-point Radic determinant against the oracle.
+
+Every case prints its identity before the GPU call so a failing run names it."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+import workloads
+from tests.parity import TOL, assert_close, normaliser, to_device
+
+pytestmark = pytest.mark.gpu
+
+radic = pytest.importorskip("paper_1508_01326_amd")
+
+
+@pytest.fixture(autouse=True)
+def _reset_launch():
+    radic.set_launch(0, 0)
+    radic.set_fallback_tau(1.0 / 1024)
+    yield
+    radic.set_launch(0, 0)
+    radic.set_fallback_tau(1.0 / 1024)
+
+
+SHAPES = [(1, 1), (1, 7), (1, 200), (2, 2), (2, 9), (2, 150), (3, 3), (3, 20), (4, 17), (5, 14), (5, 21),
+          (6, 13), (6, 18), (7, 16), (7, 19), (8, 8), (8, 17), (8, 20), (9, 18), (10, 16), (11, 15), (12, 12),
+          (12, 15)]
+
+
+def run_case(A, precision, what):
+    print(f"[case] {what} shape={A.shape} precision={precision}", flush=True)
+    return radic.radic_det(to_device(A), precision=precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_shapes(shape, precision):
+    m, n = shape
+    A = workloads.random_float(m, n, seed=m * 1000 + n)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, precision, f"random {shape}")
+    assert got["status"] == 0
+    assert got["n_subsets"] == math.comb(n, m)
+    S = normaliser(ref["abs_sum"], A)
+    assert_close(got["value"], ref["value"], S, TOL[precision], f"value {shape} {precision}")
+    assert_close(got["abs_sum"], ref["abs_sum"], ref["abs_sum"], TOL[precision] * 10, "abs_sum")
+    if precision == "fp64":
+        assert got["n_fallback"] == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_workload1_exact(precision):
+    A = workloads.single_matrix(1)
+    ref = oracle.radic_f64(A)
+    ex = float(exact.radic_subset_dp(A))
+    got = run_case(A, precision, "workload1 5x14")
+    assert_close(got["value"], ex, ref["abs_sum"], TOL[precision], "workload 1 vs exact")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_workload2_full(precision):
+    A = workloads.single_matrix(2)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, precision, "workload2 8x32")
+    assert got["n_subsets"] == 10518300
+    assert_close(got["value"], ref["value"], ref["abs_sum"], TOL[precision], "workload 2")
+    assert_close(got["abs_sum"], ref["abs_sum"], ref["abs_sum"], 10 * TOL[precision], "abs_sum")
+
+
+def test_subset_terms_and_columns(golden):
+    # exported terms against the oracle term by term, columns against Table 2
+    import torch
+    A = workloads.random_float(5, 8, seed=77)
+    print("[case] export 5x8", flush=True)
+    terms, cols = radic.radic_det_subsets(to_device(A), 0, 56, precision="fp64", with_cols=True)
+    for r in golden("table2_subsets_n8_m5.txt"):
+        q = int(r[0])
+        assert list(cols[q]) == [int(x) for x in r[1:]]
+        t, _ = oracle.subset_term_f64(A, q)
+        assert abs(terms[q] - t) <= 1e-13 * (abs(t) + 1e-300) + 1e-15
+    # a ragged window of a larger space, both precisions
+    B = workloads.random_float(8, 32, seed=5)
+    total = math.comb(32, 8)
+    for prec, tol in (("fp64", 1e-12), ("fp32_bulk", 1e-4)):
+        q0, cnt = total // 3 + 17, 1001
+        print(f"[case] export 8x32 window {prec}", flush=True)
+        terms, cols = radic.radic_det_subsets(to_device(B), q0, cnt, precision=prec, with_cols=True)
+        for k in range(0, cnt, 37):
+            t, J = oracle.subset_term_f64(B, q0 + k)
+            assert list(cols[k]) == J
+            assert abs(terms[k] - t) <= tol * (abs(t) + 1.0), (k, terms[k], t)
+
+
+def test_rank_ranges_partition():
+    A = workloads.random_float(7, 19, seed=3)
+    total = math.comb(19, 7)
+    ref = oracle.radic_f64(A)
+    cuts = [0, 1, 63, 64 * 8 + 5, total // 2, total - 1, total]
+    s = 0.0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        print(f"[case] range [{a},{b})", flush=True)
+        r = radic.radic_det_range(to_device(A), a, b - a)
+        assert r["n_subsets"] == b - a
+        part = oracle.radic_f64(A, q0=a, count=b - a)
+        assert_close(r["value"], part["value"], ref["abs_sum"], 1e-12, f"range {a}")
+        s += r["value"]
+    assert_close(s, ref["value"], ref["abs_sum"], 1e-12, "sum of ranges")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_bitwise_reproducible(precision):
+    A = workloads.random_float(8, 24, seed=11)
+    r1 = run_case(A, precision, "repro a")
+    r2 = run_case(A, precision, "repro b")
+    assert r1["hi"] == r2["hi"] and r1["lo"] == r2["lo"] and r1["abs_sum"] == r2["abs_sum"]
+
+
+@pytest.mark.parametrize("spl,block", [(1, 64), (3, 128), (16, 256), (5, 1024)])
+def test_launch_shapes(spl, block):
+    A = workloads.random_float(6, 22, seed=12)
+    ref = oracle.radic_f64(A)
+    radic.set_launch(spl, block)
+    for prec in ("fp64", "fp32_bulk"):
+        got = run_case(A, prec, f"launch spl={spl} block={block}")
+        assert_close(got["value"], ref["value"], ref["abs_sum"], TOL[prec], f"launch {spl},{block}")
+
+
+def test_degenerate_inputs():
+    import torch
+    # m > n: zero by Definition 3
+    got = run_case(np.ones((4, 3)), "fp64", "m>n")
+    assert got["value"] == 0.0 and got["status"] == 0
+    # m == n: the ordinary determinant
+    rng = np.random.default_rng(3)
+    for k in (1, 2, 5, 9, 12):
+        A = rng.standard_normal((k, k))
+        for prec in ("fp64", "fp32_bulk"):
+            got = run_case(A, prec, f"square {k}")
+            d = np.linalg.det(A)
+            assert abs(got["value"] - d) <= TOL[prec] * max(abs(d), 1.0) * 10
+    # one row: alternating sum
+    a = rng.standard_normal((1, 33))
+    got = run_case(a, "fp64", "one row")
+    assert abs(got["value"] - sum((-1) ** j * a[0, j] for j in range(33))) <= 1e-13 * np.abs(a).sum()
+    # an all-zero column and two equal rows
+    A = rng.standard_normal((5, 12))
+    A[:, 4] = 0.0
+    ref = oracle.radic_f64(A)
+    for prec in ("fp64", "fp32_bulk"):
+        got = run_case(A, prec, "zero column")
+        assert_close(got["value"], ref["value"], ref["abs_sum"], TOL[prec], "zero column")
+    A = rng.standard_normal((5, 12))
+    A[3] = A[1]
+    for prec in ("fp64", "fp32_bulk"):
+        got = run_case(A, prec, "equal rows")
+        assert_close(got["value"], 0.0, exact.hadamard_sum(A), TOL[prec], "equal rows")
+
+
+def test_nonfinite_input_reported():
+    A = np.random.default_rng(4).standard_normal((3, 9))
+    A[1, 5] = np.nan
+    for prec in ("fp64", "fp32_bulk"):
+        got = run_case(A, prec, "nan input")
+        assert got["status"] == radic.RADIC_ENONFINITE
+        assert math.isnan(got["value"])
+    A[1, 5] = np.inf
+    got = run_case(A, "fp64", "inf input")
+    assert got["status"] == radic.RADIC_ENONFINITE
+
+
+def test_strided_matrix():
+    import torch
+    base = workloads.random_float(6, 30, seed=21)
+    A = to_device(base)[:, 3:20]      # lda = 30, n = 17
+    ref = oracle.radic_f64(base[:, 3:20])
+    print("[case] strided 6x17 lda 30", flush=True)
+    got = radic.radic_det(A)
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-12, "strided")
+
+
+# ------------------------------------------------------------------ FP32-bulk fallback
+def test_fallback_forced_everywhere_is_fp64_accurate():
+    # tau = +inf refactors every minor in double (wave-cooperative LU)
+    A = workloads.random_float(6, 15, seed=31)
+    ref = oracle.radic_f64(A)
+    radic.set_fallback_tau(float("inf"))
+    got = run_case(A, "fp32_bulk", "tau=inf")
+    assert got["n_fallback"] == math.comb(15, 6)
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-12, "all fallback")
+
+
+def test_fallback_disabled():
+    A = workloads.random_float(6, 15, seed=32)
+    ref = oracle.radic_f64(A)
+    radic.set_fallback_tau(0.0)
+    got = run_case(A, "fp32_bulk", "tau=0")
+    assert got["n_fallback"] == 0
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-5, "no fallback")
+
+
+def test_fallback_near_dependent_rows():
+    # rows 0 and m-1 nearly equal: every minor nearly singular, float LU loses
+    # most digits; the fallback must catch them
+    A = workloads.near_dependent_rows(6, 16, seed=33, eps=1e-6)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, "fp32_bulk", "near dependent rows")
+    assert got["n_fallback"] > 0
+    S = max(ref["abs_sum"], 1e-300)
+    assert_close(got["value"], ref["value"], S, 1e-5, "near-dependent")
+    radic.set_fallback_tau(0.0)
+    bad = run_case(A, "fp32_bulk", "near dependent rows, no fallback")
+    print("error without fallback / S:", abs(bad["value"] - ref["value"]) / S)
+
+
+def test_row_scaling_wide_range():
+    # rows spanning ~1e+-30: float would overflow without the power-of-two row scaling
+    rng = np.random.default_rng(41)
+    A = rng.standard_normal((10, 14)) * (10.0 ** rng.uniform(-30, 30, size=(10, 1)))
+    ref = oracle.radic_f64(A)
+    got = run_case(A, "fp32_bulk", "wide row scales")
+    assert np.isfinite(got["value"])
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-5, "row scaling")
