@@ -62,8 +62,8 @@ typedef enum {
 typedef enum {
     RADIC_FP64 = 0,      /* every minor factored in IEEE double */
     RADIC_FP32_BULK = 1  /* minors factored in float on rows pre-scaled by exact powers of two;
-                            minors with a pivot below tau * (column scale) are refactored in
-                            double; all accumulation in double */
+                            minors whose product of capped pivot ratios falls below tau are
+                            refactored in double; all accumulation in double */
 } radic_precision;
 
 /* Workspace kinds for radic_workspace_bytes. */
@@ -124,6 +124,10 @@ typedef struct {
 
 /* Human-readable name of a status code (static string). */
 const char *radic_status_string(int status);
+
+/* Description of the last HIP failure seen by the library on the calling
+ * thread (which call failed and HIP's message), or "" if none. */
+const char *radic_last_error(void);
 
 /* Library version as major*10000 + minor*100 + patch. */
 int radic_version(void);
@@ -232,8 +236,10 @@ int radic_tune_load(const char *path);
 /* Force a launch shape (0 = tuned/default) for subsequent calls; for tests and sweeps. */
 int radic_set_launch(int subsets_per_lane, int block_size);
 /* FP32_BULK fallback threshold tau (default 2^-10): a minor is refactored in double
- * when some pivot |u_kk| < tau * s_k, s_k the largest |entry| of that minor's k-th
- * column in the row-scaled matrix.  tau = 0 disables, tau = +inf refactors all. */
+ * when prod_k min(1, |u_kk| / s_k) < tau, with u_kk the float pivots and s_k the
+ * largest |entry| of the minor's k-th column in the row-scaled matrix (so it also
+ * fires whenever a single pivot ratio is below tau).  tau = 0 disables the
+ * fallback, tau = +inf refactors every minor. */
 int radic_set_fallback_tau(double tau);
 
 /*

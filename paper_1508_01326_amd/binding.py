@@ -57,6 +57,7 @@ _dp = ctypes.POINTER(ctypes.c_double)
 SIGNATURES = {
     "radic_status_string": (ctypes.c_char_p, [_i]),
     "radic_version": (_i, []),
+    "radic_last_error": (ctypes.c_char_p, []),
     "radic_workspace_bytes": (_sz, [_i, _i, _i, _i]),
     "radic_det": (_i, [_vp, _i, _i, _i64, _i, _vp, _vp, _sz, _vp]),
     "radic_det_range": (_i, [_vp, _i, _i, _i64, _i, _u64, _u64, _vp, _vp, _sz, _vp]),
@@ -86,6 +87,8 @@ class RadicError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
         msg = status_string(status) if _lib is not None else str(status)
+        if _lib is not None and status == RADIC_EDEVICE:
+            msg += " [" + _lib.radic_last_error().decode() + "]"
         super().__init__(f"{where}: {msg}" if where else msg)
 
 
@@ -96,6 +99,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not found: build it with paper_1508_01326_amd/build.py "
                               "(there is no CPU fallback)")
+        # Load PyTorch first: its wheel carries its own HIP runtime under the same
+        # soname as the system one, and the library must bind to the runtime that
+        # owns PyTorch's streams and allocations (one runtime per process).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -97,7 +97,7 @@ __device__ int stage_matrix(const FloatJob& J, double* cd, float* cf, int* rowex
             float s = 0.f;
 #pragma unroll
             for (int i = 0; i < M; ++i) s = fmaxf(s, fabsf(cf[j * ST32 + i]));
-            cf[j * ST32 + M] = s;
+            cf[j * ST32 + M] = s > 0.f ? 1.0f / s : 0.f;   // reciprocal column scale 1/s_j
         }
         __syncthreads();
     }
@@ -204,8 +204,8 @@ __device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p) {
 // column, flips `neg` once per row exchange and, for FP32 (CHECK), raises `flag`
 // when a pivot falls below tau * s_k.
 template <int M, int K, typename T, bool CHECK>
-__device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool& neg, bool& flag,
-                                         const T (&s)[M], T tau) {
+__device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool& neg, float& ratio,
+                                         const T (&s)[M]) {
     if constexpr (K < M - 1) {
         unsigned best = pivot_key(a[K][K], K);
 #pragma unroll
@@ -215,7 +215,7 @@ __device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool&
         exchange_rows<M, K, T>(a, p);
         const T piv = a[K][K];
         zero |= (piv == T(0));
-        if (CHECK) flag |= !(__builtin_fabsf((float)piv) >= (float)(tau * s[K]));
+        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)s[K]);
         det *= piv;
         const T r = recip(piv);
 #pragma unroll
@@ -224,18 +224,26 @@ __device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool&
 #pragma unroll
             for (int j = K + 1; j < M; ++j) a[i][j] = __builtin_fma(-l, a[K][j], a[i][j]);
         }
-        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, flag, s, tau);
+        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, ratio, s);
     }
 }
 
-// Determinant of the minor (0 for an exactly zero pivot column).
+// Determinant of the minor (0 for an exactly zero pivot column).  For FP32
+// (CHECK) `flag` is raised when prod_k min(1, |u_kk| / s_k) < tau, s_k the largest
+// magnitude in the minor's k-th column of the row-scaled matrix (s holds 1/s_k):
+// the minor is then relatively ill-conditioned, float elimination may have lost
+// too many digits, and the minor is refactored in double.
 template <int M, typename T, bool CHECK>
 __device__ __forceinline__ T lu_det(T (&a)[M][M], bool& neg, bool& flag, const T (&s)[M], T tau) {
     T det = T(1);
     bool zero = false;
-    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, flag, s, tau);
+    float ratio = 1.0f;
+    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, ratio, s);
     const T last = a[M - 1][M - 1];
-    if (CHECK) flag |= !(__builtin_fabsf((float)last) >= (float)(tau * s[M - 1]));
+    if (CHECK) {
+        ratio *= __saturatef(__builtin_fabsf((float)last) * (float)s[M - 1]);
+        flag |= !(ratio >= (float)tau);
+    }
     det *= last;
     return zero ? T(0) : det;
 }
@@ -303,7 +311,7 @@ __device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
 // Refactor every queued minor in double; lane 0 accumulates the terms.
 template <int M, bool EXPORT>
 __device__ void flush_fallback(const FloatJob& J, const double* cd, unsigned* queue, int count, double* W,
-                               int lane, double& hi, double& lo, double& ab) {
+                               int lane, double& hi, double& lo, double& ab, int scale_exp) {
     for (int e = 0; e < count; ++e) {
         int c[M];
         unpack_cols<M>(queue + 4 * e, c);
@@ -316,7 +324,7 @@ __device__ void flush_fallback(const FloatJob& J, const double* cd, unsigned* qu
             hi = s;
             lo += err;
             ab += fabs(d);
-            if (EXPORT) J.terms[off] = term;
+            if (EXPORT) J.terms[off] = ldexp(term, scale_exp);
         }
         wave_lds_sync();
     }
@@ -324,7 +332,7 @@ __device__ void flush_fallback(const FloatJob& J, const double* cd, unsigned* qu
 
 // ---------------------------------------------------------------- main kernel
 template <int M, bool F32, bool EXPORT>
-__global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
+__global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
     using T = typename std::conditional<F32, float, double>::type;
     constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -355,6 +363,10 @@ __global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
         J.header->scale_exp = se;
     }
 
+    // exported terms are returned in the units of A (row scaling undone)
+    int scale_exp = 0;
+    if (F32 && EXPORT)
+        for (int i = 0; i < M; ++i) scale_exp += rowexp[i];
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nfb = 0;
     int qcount = 0;   // wave-uniform fallback queue length
@@ -394,7 +406,7 @@ __global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
                 lo += err;
                 ab += fabs(d);
                 if (EXPORT) {
-                    J.terms[off0 + s] = term;
+                    J.terms[off0 + s] = F32 ? ldexp(term, scale_exp) : term;
                 }
             }
             if (EXPORT && valid && J.cols) {
@@ -418,7 +430,7 @@ __global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
                     qcount += __popcll(fm);
                     if (qcount > kFallbackCap - kWave) {
                         wave_lds_sync();
-                        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab);
+                        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
                         qcount = 0;
                     }
                 }
@@ -428,7 +440,7 @@ __global__ __launch_bounds__(256) void k_radic_float(FloatJob J) {
     }
     if (F32 && qcount > 0) {
         wave_lds_sync();
-        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab);
+        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
     }
     if (EXPORT) return;
 
@@ -508,6 +520,7 @@ __global__ void k_write_zero_result(radic_f64_result* out) {
 template <int M, bool F32, bool EXPORT>
 static hipError_t launch_m(const FloatJob& J, int grid, int block, hipStream_t s) {
     const int lds = lds_bytes<M, F32>(J.n, block / kWave);
+    (void)hipGetLastError();   // clear an error left by an earlier, unrelated call
     hipLaunchKernelGGL((k_radic_float<M, F32, EXPORT>), dim3(grid), dim3(block), lds, s, J);
     return hipGetLastError();
 }
@@ -545,11 +558,13 @@ hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, i
 
 hipError_t launch_finalize_float(const Partial* parts, int G, const DetHeader* h, radic_f64_result* out,
                                  unsigned long long count, int use_scale, hipStream_t s) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(256), 0, s, parts, G, h, out, count, use_scale);
     return hipGetLastError();
 }
 
 hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s) {
+    (void)hipGetLastError();
     hipLaunchKernelGGL(k_write_zero_result, dim3(1), dim3(1), 0, s, out);
     return hipGetLastError();
 }

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -41,13 +42,24 @@ int host_binomial(int a, int b, unsigned long long* out) {
     return RADIC_OK;
 }
 
+// ---------------------------------------------------------------- error reporting
+static thread_local char g_last_error[256] = "";
+
+static int device_error(const char* what, hipError_t e) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    if (std::getenv("RADIC_LOG")) std::fprintf(stderr, "[radic] %s\n", g_last_error);
+    return RADIC_EDEVICE;
+}
+
 // ---------------------------------------------------------------- per-device state
 static std::mutex g_mu;
 static bool g_dev_ready[64];
 
 static int ensure_device() {
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return RADIC_EDEVICE;
+    hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return device_error("hipGetDevice", ge);
+    if (dev < 0 || dev >= 64) return RADIC_ENOTSUP;
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_dev_ready[dev]) return RADIC_OK;
     std::vector<unsigned long long> t((size_t)kBinomRows * kBinomCols, 0);
@@ -57,7 +69,8 @@ static int ensure_device() {
             if (host_binomial(x, y, &v) != RADIC_OK) v = ~0ull;   // saturate; never used
             t[(size_t)x * kBinomCols + y] = v;
         }
-    if (upload_binomials(t.data()) != hipSuccess) return RADIC_EDEVICE;
+    hipError_t ue = upload_binomials(t.data());
+    if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
     return RADIC_OK;
 }
@@ -142,6 +155,11 @@ static int float_common_checks(const double* dA, int m, int n, long long lda, in
     return RADIC_OK;
 }
 
+static int zero_result(radic_f64_result* out, hipStream_t s) {
+    hipError_t e = launch_zero_result(out, s);
+    return e == hipSuccess ? RADIC_OK : device_error("launch of the zero-result kernel", e);
+}
+
 static int grid_for(unsigned long long chunks, int block) {
     const unsigned long long wave_chunks = (chunks + kWave - 1) / kWave;
     const unsigned long long wpb = (unsigned long long)(block / kWave);
@@ -158,7 +176,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     int rc = float_common_checks(dA, m, n, lda, prec);
     if (rc != RADIC_OK) return rc;
     if ((rc = ensure_device()) != RADIC_OK) return rc;
-    if (m > n) return launch_zero_result(dOut, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    if (m > n) return zero_result(dOut, stream);
     unsigned long long total = 0;
     if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
     if ((rc = check_workspace(dWork, work_bytes, det_workspace_bytes())) != RADIC_OK) return rc;
@@ -169,7 +187,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         if (q_begin >= total) count = 0;
         else if (count > total - q_begin) count = total - q_begin;
     }
-    if (count == 0) return launch_zero_result(dOut, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    if (count == 0) return zero_result(dOut, stream);
     Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
     if (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) return RADIC_ENOTSUP;
 
@@ -195,9 +213,9 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         ProfScope ps(stream);
         e = launch_float(m, prec, false, J, grid, sh.block, stream);
     }
-    if (e != hipSuccess) return RADIC_EDEVICE;
+    if (e != hipSuccess) return device_error("launch of the enumeration kernel", e);
     e = launch_finalize_float(J.partials, grid, J.header, dOut, count, prec == RADIC_FP32_BULK, stream);
-    return e == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
 }
 
 }  // namespace radic
@@ -221,6 +239,8 @@ const char* radic_status_string(int status) {
 }
 
 int radic_version(void) { return 100; }
+
+const char* radic_last_error(void) { return g_last_error; }
 
 size_t radic_workspace_bytes(int kind, int m, int n, int batch) {
     switch (kind) {
@@ -274,7 +294,8 @@ int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uin
     J.terms = dTerms;
     J.cols = dCols;
     const int grid = grid_for(J.chunks, sh.block);
-    return launch_float(m, prec, true, J, grid, sh.block, stream) == hipSuccess ? RADIC_OK : RADIC_EDEVICE;
+    hipError_t e = launch_float(m, prec, true, J, grid, sh.block, stream);
+    return e == hipSuccess ? RADIC_OK : device_error("launch of the export kernel", e);
 }
 
 int radic_det_int_exact(const int32_t*, int, int, int64_t, uint32_t*, int, int*, int*, void*, size_t, hipStream_t) {
@@ -299,7 +320,8 @@ int radic_tune_load(const char*) { return RADIC_ENOTSUP; }
 
 int radic_set_launch(int subsets_per_lane, int block_size) {
     if (subsets_per_lane < 0 || subsets_per_lane > 4096) return RADIC_EINVAL;
-    if (block_size != 0 && (block_size < 64 || block_size > 1024 || block_size % 64)) return RADIC_EINVAL;
+    // kernels are compiled for at most kMaxBlock threads per workgroup
+    if (block_size != 0 && (block_size < kWave || block_size > kMaxBlock || block_size % kWave)) return RADIC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_force_spl = subsets_per_lane;
     g_force_block = block_size;

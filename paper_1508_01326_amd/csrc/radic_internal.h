@@ -9,6 +9,7 @@
 namespace radic {
 
 constexpr int kWave = 64;            // CDNA4 wavefront width
+constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration kernel
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;

@@ -98,6 +98,8 @@ def test_launch_and_tau_setters_validate():
     L = radic.lib()
     assert L.radic_set_launch(-1, 0) == radic.RADIC_EINVAL
     assert L.radic_set_launch(8, 96) == radic.RADIC_EINVAL
+    assert L.radic_set_launch(8, 512) == radic.RADIC_EINVAL     # above the kernels' launch bounds
+    assert L.radic_set_launch(8, 1024) == radic.RADIC_EINVAL
     assert L.radic_set_launch(0, 0) == radic.RADIC_OK
     assert L.radic_set_fallback_tau(float("nan")) == radic.RADIC_EINVAL
     assert L.radic_set_fallback_tau(-1.0) == radic.RADIC_EINVAL
