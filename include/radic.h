@@ -255,6 +255,13 @@ int radic_profile_read(double *hTotalMs, int *hLaunches);
  * dropped).  Clears like radic_profile_read. */
 int radic_profile_read_launches(double *hMs, int capacity, int *hCount);
 
+/* Prime set of the exact path: by default the 24 largest primes below 2^31,
+ * in decreasing order.  Tests may substitute other odd primes (e.g. tiny ones,
+ * so that zero pivots modulo p occur): hPrimes[0..count-1], each prime,
+ * 3 <= p < 2^31, distinct, count <= RADIC_MAX_PRIMES; count = 0 restores the
+ * default.  Applies to later calls on every device.  EINVAL on a bad list. */
+int radic_set_prime_set(const uint32_t *hPrimes, int count);
+
 /* Host-side combinatorics used by the launchers, exported for testing:
  * binomial with overflow detection (returns EOVERFLOW), dictionary-order
  * unranking (1-based columns into hCols), and the i-th prime used by the exact path. */

@@ -78,6 +78,7 @@ SIGNATURES = {
     "radic_host_binomial": (_i, [_i, _i, _u64p]),
     "radic_host_unrank": (_i, [_i, _i, _u64, _ip]),
     "radic_host_prime": (_i, [_i, _u32p]),
+    "radic_set_prime_set": (_i, [_u32p, _i]),
 }
 
 _lib = None
@@ -279,6 +280,12 @@ def host_unrank(m, n, q):
     cols = (ctypes.c_int * m)()
     _check(lib().radic_host_unrank(int(m), int(n), int(q), cols), "radic_host_unrank")
     return list(cols)
+
+
+def set_prime_set(primes=()):
+    primes = list(primes)
+    arr = (ctypes.c_uint32 * max(len(primes), 1))(*primes)
+    _check(lib().radic_set_prime_set(arr, len(primes)), "radic_set_prime_set")
 
 
 def host_prime(i):

@@ -20,15 +20,9 @@
 // of Section 6), so results are bitwise reproducible for a given launch shape.
 #include <type_traits>
 
-#include "radic_internal.h"
+#include "enumerate.h"
 
 namespace radic {
-
-// Binomial coefficients C(x, y), x < kBinomRows, y < kBinomCols, saturated at
-// 2^64-1; filled once per device by the host.
-constexpr int kBinomRows = RADIC_MAX_N + 1;
-constexpr int kBinomCols = 16;
-__device__ unsigned long long g_binom[kBinomRows * kBinomCols];
 
 // ---------------------------------------------------------------- LDS layout
 // Columns are stored contiguously with a stride (in 16-byte groups) chosen odd so
@@ -40,30 +34,42 @@ template <int M> struct Layout {
     static constexpr int st32 = 4 * g32;                  // floats per column (+1 slot: column scale)
 };
 
-__host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
-
-template <int M> __host__ __device__ constexpr int binom_bytes(int n) { return align16(n * M * 8); }
-
 // Per-wave fallback region: queue of 16-byte entries + M x M double scratch.
 template <int M> __host__ __device__ constexpr int fallback_wave_bytes() {
     return kFallbackCap * 16 + align16(M * M * 8);
 }
 
+// Per-wave copy of the columns the lanes gather from, rows in the wave's order.
+template <int M, bool F32> __host__ __device__ int wave_copy_bytes(int n) {
+    return F32 ? align16(n * Layout<M>::st32 * 4) : align16(n * Layout<M>::st64 * 8);
+}
+
+// LDS per workgroup: binomial table, master copies of A (double; float for F32),
+// then per wave: its row-ordered copy and (F32) its fallback region.
 template <int M, bool F32> __host__ __device__ int lds_bytes(int n, int waves) {
     int b = binom_bytes<M>(n) + align16(n * Layout<M>::st64 * 8);
-    if (F32) b += align16(n * Layout<M>::st32 * 4) + waves * fallback_wave_bytes<M>();
+    if (F32) b += align16(n * Layout<M>::st32 * 4);
+    b += waves * (wave_copy_bytes<M, F32>(n) + (F32 ? fallback_wave_bytes<M>() : 0));
     return b;
 }
 
-// ---------------------------------------------------------------- staging
-template <int M>
-__device__ void stage_binomials(unsigned long long* bt, int n) {
-    for (int e = threadIdx.x; e < n * M; e += blockDim.x) {
-        int x = e / M, y = e - x * M;
-        bt[e] = g_binom[x * kBinomCols + y];
+// Rewrite the wave's copy with rows in the order `perm` (copy row r = master row
+// perm[r]); the column-scale slot of the float layout is row independent.
+template <int M, typename T>
+__device__ void write_wave_copy(T* dst, const T* master, int stride, int n, unsigned long long perm, int lane,
+                                bool scale_slot) {
+    wave_lds_sync();
+    for (int e = lane; e < n * M; e += kWave) {
+        const int j = e / M, r = e - j * M;
+        const int src = (int)((perm >> (4 * r)) & 15ull);
+        dst[j * stride + r] = master[j * stride + src];
     }
+    if (scale_slot)
+        for (int j = lane; j < n; j += kWave) dst[j * stride + M] = master[j * stride + M];
+    wave_lds_sync();
 }
 
+// ---------------------------------------------------------------- staging
 // Stage A column-major into LDS (double copy; for F32 also the row-scaled float
 // copy and the per-column scale).  Returns the workgroup-wide non-finite flag.
 template <int M, bool F32>
@@ -104,52 +110,6 @@ __device__ int stage_matrix(const FloatJob& J, double* cd, float* cf, int* rowex
     return bad;
 }
 
-// ---------------------------------------------------------------- sequences
-// Dictionary-order unranking (Section 4): at place k the sequences that put the
-// value c there number C(n-1-c, M-1-k) (0-based c); step c to the right while q
-// can pay for them.  bt[x*M + y] = C(x, y).
-template <int M>
-__device__ __forceinline__ void unrank(unsigned long long q, int n, const unsigned long long* bt, int (&col)[M]) {
-    int c = 0;
-#pragma unroll
-    for (int k = 0; k < M; ++k) {
-        for (;;) {
-            unsigned long long w = bt[(n - 1 - c) * M + (M - 1 - k)];
-            if (q < w) break;
-            q -= w;
-            ++c;
-        }
-        col[k] = c;
-        ++c;
-    }
-}
-
-// Dictionary successor (Section 5): the rightmost place still below its maximum
-// n-M+j moves up by one and the places after it follow consecutively.  Written
-// without branches; from the last member it wraps to the first (callers never
-// use that value).
-template <int M>
-__device__ __forceinline__ void successor(int (&col)[M], int n) {
-    int ip = -1, t = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-        bool nf = col[j] < n - M + j;
-        ip = nf ? j : ip;
-        t = nf ? col[j] - j + 1 : t;
-    }
-#pragma unroll
-    for (int j = 0; j < M; ++j) col[j] = (j >= ip) ? t + j : col[j];
-}
-
-// Parity of r + s in (-1)^(r+s): r = M(M+1)/2, s = sum of 1-based columns.
-template <int M>
-__device__ __forceinline__ bool radic_sign_odd(const int (&col)[M]) {
-    int s = M * (M + 1) / 2 + M;
-#pragma unroll
-    for (int j = 0; j < M; ++j) s += col[j];
-    return s & 1;
-}
-
 // ---------------------------------------------------------------- LU building blocks
 template <int M, typename T>
 __device__ __forceinline__ void gather(T (&a)[M][M], const T* base, int stride, const int (&col)[M]) {
@@ -181,13 +141,22 @@ __device__ __forceinline__ void gather(T (&a)[M][M], const T* base, int stride, 
 
 // Bring each lane's pivot row p into row K with selects.  Only candidate rows
 // that some lane of the wave chose are visited (a wave-uniform test), so a step
-// on which the whole wave keeps row K costs one ballot.
+// on which the whole wave keeps row K costs one ballot per candidate.  When every
+// lane of the wave chose the same row i, the exchange (K, i) is recorded in the
+// wave's row order `perm` (4 bits per position) and its parity flipped, so that
+// the next minors are gathered with that exchange already applied.
 template <int M, int K, typename T>
-__device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p) {
+__device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p, unsigned long long& perm, int& perm_odd) {
 #pragma unroll
     for (int i = K + 1; i < M; ++i) {
         const bool c = (p == i);
-        if (__ballot(c)) {
+        const unsigned long long mask = __ballot(c);
+        if (mask) {
+            if (mask == ~0ull) {
+                const unsigned long long x = ((perm >> (4 * K)) ^ (perm >> (4 * i))) & 15ull;
+                perm ^= (x << (4 * K)) | (x << (4 * i));
+                perm_odd ^= 1;
+            }
 #pragma unroll
             for (int j = K; j < M; ++j) {
                 const T x = a[K][j], y = a[i][j];
@@ -205,14 +174,14 @@ __device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p) {
 // when a pivot falls below tau * s_k.
 template <int M, int K, typename T, bool CHECK>
 __device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool& neg, float& ratio,
-                                         const T (&s)[M]) {
+                                         const T (&s)[M], unsigned long long& perm, int& perm_odd) {
     if constexpr (K < M - 1) {
         unsigned best = pivot_key(a[K][K], K);
 #pragma unroll
         for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(a[i][K], i));
         const int p = pivot_row(best);
         neg ^= (p != K);
-        exchange_rows<M, K, T>(a, p);
+        exchange_rows<M, K, T>(a, p, perm, perm_odd);
         const T piv = a[K][K];
         zero |= (piv == T(0));
         if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)s[K]);
@@ -222,9 +191,9 @@ __device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool&
         for (int i = K + 1; i < M; ++i) {
             const T l = a[i][K] * r;
 #pragma unroll
-            for (int j = K + 1; j < M; ++j) a[i][j] = __builtin_fma(-l, a[K][j], a[i][j]);
+            for (int j = K + 1; j < M; ++j) a[i][j] = fma_t(-l, a[K][j], a[i][j]);
         }
-        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, ratio, s);
+        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, ratio, s, perm, perm_odd);
     }
 }
 
@@ -234,11 +203,12 @@ __device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool&
 // the minor is then relatively ill-conditioned, float elimination may have lost
 // too many digits, and the minor is refactored in double.
 template <int M, typename T, bool CHECK>
-__device__ __forceinline__ T lu_det(T (&a)[M][M], bool& neg, bool& flag, const T (&s)[M], T tau) {
+__device__ __forceinline__ T lu_det(T (&a)[M][M], bool& neg, bool& flag, const T (&s)[M], T tau,
+                                    unsigned long long& perm, int& perm_odd) {
     T det = T(1);
     bool zero = false;
     float ratio = 1.0f;
-    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, ratio, s);
+    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, ratio, s, perm, perm_odd);
     const T last = a[M - 1][M - 1];
     if (CHECK) {
         ratio *= __saturatef(__builtin_fabsf((float)last) * (float)s[M - 1]);
@@ -348,8 +318,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
     unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
     double* cd = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
     float* cf = reinterpret_cast<float*>(smem + binom_bytes<M>(n) + align16(n * ST64 * 8));
-    unsigned char* fb = smem + binom_bytes<M>(n) + align16(n * ST64 * 8) + align16(n * ST32 * 4) +
-                        wave * fallback_wave_bytes<M>();
+    unsigned char* wr = smem + binom_bytes<M>(n) + align16(n * ST64 * 8) + (F32 ? align16(n * ST32 * 4) : 0) +
+                        wave * (wave_copy_bytes<M, F32>(n) + (F32 ? fallback_wave_bytes<M>() : 0));
+    T* wcopy = reinterpret_cast<T*>(wr);
+    unsigned char* fb = wr + wave_copy_bytes<M, F32>(n);
     unsigned* queue = reinterpret_cast<unsigned*>(fb);
     double* W = reinterpret_cast<double*>(fb + kFallbackCap * 16);
 
@@ -370,9 +342,16 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nfb = 0;
     int qcount = 0;   // wave-uniform fallback queue length
-    const T* colbase = F32 ? reinterpret_cast<const T*>(cf) : reinterpret_cast<const T*>(cd);
+    const T* master = F32 ? reinterpret_cast<const T*>(cf) : reinterpret_cast<const T*>(cd);
     const int colstride = F32 ? ST32 : ST64;
     const T tau = (T)J.tau;
+    // the wave's row order (4 bits per position, identity to start) and its parity
+    unsigned long long perm = 0;
+#pragma unroll
+    for (int r = 0; r < M; ++r) perm |= (unsigned long long)r << (4 * r);
+    int perm_odd = 0;
+    write_wave_copy<M, T>(wcopy, master, colstride, n, perm, lane, F32);
+    const T* colbase = wcopy;
 
     const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
     const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
@@ -393,9 +372,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
 #pragma unroll
                 for (int j = 0; j < M; ++j) sc[j] = colbase[col[j] * colstride + M];
             }
-            bool neg = radic_sign_odd<M>(col);
+            // the minor was gathered with rows in the wave's order: det(P A_J) = sgn(P) det(A_J)
+            bool neg = radic_sign_odd<M>(col) ^ (perm_odd != 0);
             bool flag = false;
-            const T det = lu_det<M, T, F32>(a, neg, flag, sc, tau);
+            const unsigned long long perm_before = perm;
+            const T det = lu_det<M, T, F32>(a, neg, flag, sc, tau, perm, perm_odd);
             flag = flag && valid;
             if (valid && !flag) {
                 const double d = (double)det;
@@ -435,6 +416,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
                     }
                 }
             }
+            if (perm != perm_before) write_wave_copy<M, T>(wcopy, master, colstride, n, perm, lane, false);
             successor<M>(col, n);
         }
     }
@@ -569,8 +551,6 @@ hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t upload_binomials(const unsigned long long* host_table) {
-    return hipMemcpyToSymbol(HIP_SYMBOL(g_binom), host_table, sizeof(unsigned long long) * kBinomRows * kBinomCols);
-}
+hipError_t upload_binomials_float(const unsigned long long* host_table) { return upload_binomial_table(host_table); }
 
 }  // namespace radic

@@ -1,0 +1,444 @@
+// Exact Radic determinant of an int32 matrix by modular arithmetic.
+//
+// The exact result S = sum_J (-1)^(r+s) det(A_J) (Definition 3, eq. (1)) is an
+// integer with |S| <= sum_J prod_{j in J} ||a_j||_2 = e_m(||a_1||, ..., ||a_n||)
+// (Hadamard's inequality per minor).  For k primes p_i < 2^31 whose product
+// exceeds twice that bound, S is recovered from S mod p_i by the Chinese
+// remainder theorem (Garner's mixed-radix form) in the symmetric range.
+//
+// Per lane and prime, each minor is eliminated fraction-free modulo p
+// (Bareiss-type row updates row_i <- u_kk row_i - a_ik row_k, pivot = first row
+// with a nonzero entry mod p).  The divisions that make Bareiss's recurrence
+// exact are not done per step; since every update scales the rows below by the
+// pivot, det(A_J) = prod_k u_kk / prod_{k<M-1} u_kk^(M-1-k) mod p, and the lane
+// keeps its running sum as one fraction num/den, so a single modular inverse per
+// workgroup replaces all per-minor divisions.  Residues are held in doubles
+// (exact below 2^53) and multiplied with an error-free product and a floor-based
+// reduction (double products of 31-bit operands are split with an FMA).
+#include "enumerate.h"
+
+namespace radic {
+
+static __device__ double g_prime[RADIC_MAX_PRIMES];
+static __device__ double g_prime_inv[RADIC_MAX_PRIMES];
+
+struct IntHeader {
+    int n_primes;       // primes needed for the bound
+    int status;         // RADIC_OK or RADIC_EOVERFLOW (bound needs more than the prime set)
+    double bound_log2;  // log2 of the bound on |S|
+};
+
+struct IntResult {
+    int status;
+    int sign;
+    int mag_len;
+    int n_primes;
+    unsigned mag[RADIC_MAX_PRIMES + 1];
+    unsigned residue[RADIC_MAX_PRIMES];
+};
+
+struct IntJob {
+    const int* A;
+    long long lda;
+    int m, n;
+    unsigned long long count;
+    unsigned long long chunks;
+    int spl;
+    int grid_x;
+    double* partials;    // [prime][grid_x] residues
+    IntHeader* header;
+};
+
+template <int M> struct IntLayout {
+    static constexpr int g64 = (((M + 1) / 2) % 2 == 0) ? (M + 1) / 2 + 1 : (M + 1) / 2;
+    static constexpr int st = 2 * g64;   // doubles per column
+};
+
+template <int M> __host__ __device__ int int_lds_bytes(int n) {
+    return binom_bytes<M>(n) + align16(n * IntLayout<M>::st * 8);
+}
+
+// ---------------------------------------------------------------- modular arithmetic on exact doubles
+__device__ __forceinline__ double mod_fix(double r, double p) {
+    r = r < 0.0 ? r + p : r;
+    return r >= p ? r - p : r;
+}
+
+// a*b mod p for 0 <= a, b < p < 2^31: h + l = a*b exactly (FMA split); q is
+// floor(a*b/p) up to +-1, so h - q p + l lies in [-p, 2p) and is exact.
+__device__ __forceinline__ double mulmod(double a, double b, double p, double pinv) {
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double q = __builtin_floor(h * pinv);
+    const double r = __builtin_fma(-q, p, h) + l;
+    return mod_fix(r, p);
+}
+
+__device__ __forceinline__ double addmod(double a, double b, double p) {
+    const double r = a + b;
+    return r >= p ? r - p : r;
+}
+
+__device__ __forceinline__ double submod(double a, double b, double p) {
+    const double r = a - b;
+    return r < 0.0 ? r + p : r;
+}
+
+// x^(p-2) mod p (Fermat), x != 0
+__device__ double invmod(double x, double p, double pinv) {
+    unsigned long long e = (unsigned long long)p - 2ull;
+    double r = 1.0, b = x;
+    while (e) {
+        if (e & 1ull) r = mulmod(r, b, p, pinv);
+        b = mulmod(b, b, p, pinv);
+        e >>= 1;
+    }
+    return r;
+}
+
+// ---------------------------------------------------------------- bound and prime count
+__global__ __launch_bounds__(256) void k_int_bound(const int* A, int m, int n, long long lda, IntHeader* h,
+                                                   int prime_count) {
+    __shared__ double norms[RADIC_MAX_N];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double a = (double)A[(long long)i * lda + j];
+            s = __builtin_fma(a, a, s);
+        }
+        norms[j] = sqrt(s) * (1.0 + 1e-12);   // rounded up
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        // e_m of the column norms by the recurrence e_k += x e_{k-1} (all terms >= 0)
+        double e[RADIC_MAX_M + 1];
+        e[0] = 1.0;
+        for (int k = 1; k <= m; ++k) e[k] = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int k = m; k >= 1; --k) e[k] = __builtin_fma(norms[j], e[k - 1], e[k]);
+        const double bound = e[m] * (1.0 + 1e-9) + 1.0;
+        const double need = log2(bound) + 1.0 + 1e-6;   // product of primes > 2 * bound
+        double have = 0.0;
+        int k = 0;
+        while (k < prime_count && have <= need) have += log2(g_prime[k++]);
+        h->bound_log2 = log2(bound);
+        h->n_primes = k;
+        h->status = have > need ? RADIC_OK : RADIC_EOVERFLOW;
+    }
+}
+
+// ---------------------------------------------------------------- per-lane elimination mod p
+template <int M, int K>
+__device__ __forceinline__ void exchange_rows_int(double (&a)[M][M], int p) {
+#pragma unroll
+    for (int i = K + 1; i < M; ++i) {
+        const bool c = (p == i);
+        if (__ballot(c)) {
+#pragma unroll
+            for (int j = K; j < M; ++j) {
+                const double x = a[K][j], y = a[i][j];
+                a[K][j] = c ? y : x;
+                a[i][j] = c ? x : y;
+            }
+        }
+    }
+}
+
+template <int M, int K>
+__device__ __forceinline__ void elim_steps_mod(double (&a)[M][M], double p, double pinv, double& N, double& P,
+                                               double& D, bool& zero, bool& neg) {
+    if constexpr (K < M) {
+        // pivot: first row i >= K whose entry in column K is nonzero mod p
+        unsigned best = 0;
+#pragma unroll
+        for (int i = K; i < M; ++i) best = max(best, a[i][K] != 0.0 ? (unsigned)(15 - i) : 0u);
+        const bool col_zero = (best == 0u);
+        const int piv_row = col_zero ? K : 15 - (int)best;
+        zero |= col_zero;
+        if constexpr (K < M - 1) {
+            neg ^= (piv_row != K);
+            exchange_rows_int<M, K>(a, piv_row);
+        }
+        const double u = col_zero ? 1.0 : a[K][K];
+        N = mulmod(N, u, p, pinv);
+        if constexpr (K < M - 1) {
+            P = mulmod(P, u, p, pinv);
+            D = mulmod(D, P, p, pinv);
+#pragma unroll
+            for (int i = K + 1; i < M; ++i) {
+                const double l = a[i][K];
+#pragma unroll
+                for (int j = K + 1; j < M; ++j)
+                    a[i][j] = submod(mulmod(u, a[i][j], p, pinv), mulmod(l, a[K][j], p, pinv), p);
+            }
+            elim_steps_mod<M, K + 1>(a, p, pinv, N, P, D, zero, neg);
+        }
+    }
+}
+
+// fraction (n1/d1) += (n2/d2)
+__device__ __forceinline__ void frac_add(double& n1, double& d1, double n2, double d2, double p, double pinv) {
+    n1 = addmod(mulmod(n1, d2, p, pinv), mulmod(n2, d1, p, pinv), p);
+    d1 = mulmod(d1, d2, p, pinv);
+}
+
+template <int M>
+__global__ __launch_bounds__(kMaxBlock) void k_radic_int(IntJob J) {
+    constexpr int ST = IntLayout<M>::st;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[2 * 16];
+    const int n = J.n;
+    const int waves = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    const int lane = threadIdx.x % kWave;
+    const double p = g_prime[blockIdx.y];
+    const double pinv = g_prime_inv[blockIdx.y];
+
+    unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
+    double* cr = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
+    stage_binomials<M>(bt, n);
+    for (int e = threadIdx.x; e < M * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        const double v = (double)J.A[(long long)i * J.lda + j];
+        const double q = __builtin_floor(v * pinv);
+        cr[j * ST + i] = mod_fix(__builtin_fma(-q, p, v), p);   // exact residue in [0, p)
+    }
+    __syncthreads();
+
+    double num = 0.0, den = 1.0;
+    const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
+    const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
+    for (unsigned long long wc = gwave * kWave; wc < J.chunks; wc += nwaves * kWave) {
+        const unsigned long long chunk = wc + lane;
+        const bool vchunk = chunk < J.chunks;
+        const unsigned long long off0 = vchunk ? chunk * (unsigned long long)J.spl : J.count - 1;
+        const unsigned long long left = J.count - off0;
+        const int cnt = vchunk ? (int)(left < (unsigned long long)J.spl ? left : (unsigned long long)J.spl) : 0;
+        int col[M];
+        unrank<M>(off0, n, bt, col);
+        for (int s = 0; s < J.spl; ++s) {
+            double a[M][M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double* src = cr + col[j] * ST;
+#pragma unroll
+                for (int i = 0; i + 1 < M; i += 2) {
+                    const double2 v = *reinterpret_cast<const double2*>(src + i);
+                    a[i][j] = v.x;
+                    a[i + 1][j] = v.y;
+                }
+                if (M & 1) a[M - 1][j] = src[M - 1];
+            }
+            double N = 1.0, P = 1.0, D = 1.0;
+            bool zero = false;
+            bool neg = radic_sign_odd<M>(col);
+            elim_steps_mod<M, 0>(a, p, pinv, N, P, D, zero, neg);
+            if (s < cnt && !zero) {
+                const double t = neg ? (N == 0.0 ? 0.0 : p - N) : N;
+                frac_add(num, den, t, D, p, pinv);
+            }
+            successor<M>(col, n);
+        }
+    }
+    // fixed-order butterfly over the wave, then waves in order
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        const double n2 = shfl_xor_d(num, off), d2 = shfl_xor_d(den, off);
+        frac_add(num, den, n2, d2, p, pinv);
+    }
+    if (lane == 0) {
+        red[2 * wave] = num;
+        red[2 * wave + 1] = den;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double nn = red[0], dd = red[1];
+        for (int w = 1; w < waves; ++w) frac_add(nn, dd, red[2 * w], red[2 * w + 1], p, pinv);
+        J.partials[(long long)blockIdx.y * J.grid_x + blockIdx.x] = mulmod(nn, invmod(dd, p, pinv), p, pinv);
+    }
+}
+
+// ---------------------------------------------------------------- CRT
+// Sum the workgroup residues per prime, then Garner's algorithm (mixed radix
+// digits v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
+// representative in (-P/2, P/2] as sign and 32-bit limbs.
+__device__ unsigned long long powmod_u64(unsigned long long b, unsigned long long e, unsigned long long p) {
+    unsigned long long r = 1 % p;
+    b %= p;
+    while (e) {
+        if (e & 1ull) r = (r * b) % p;
+        b = (b * b) % p;
+        e >>= 1;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_int_finalize(const double* partials, int grid_x, const IntHeader* h,
+                                                      IntResult* out) {
+    __shared__ unsigned long long res[RADIC_MAX_PRIMES];
+    const int k = h->n_primes;
+    for (int t = threadIdx.x; t < k; t += blockDim.x) {
+        const unsigned long long pr = (unsigned long long)g_prime[t];
+        unsigned long long s = 0;
+        for (int b = 0; b < grid_x; ++b) s += (unsigned long long)partials[(long long)t * grid_x + b];
+        res[t] = s % pr;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    IntResult r{};
+    r.n_primes = k;
+    r.status = h->status;
+    if (h->status != RADIC_OK) {
+        *out = r;
+        return;
+    }
+    unsigned long long pr[RADIC_MAX_PRIMES], v[RADIC_MAX_PRIMES];
+    for (int i = 0; i < k; ++i) {
+        pr[i] = (unsigned long long)g_prime[i];
+        r.residue[i] = (unsigned)res[i];
+    }
+    for (int i = 0; i < k; ++i) {
+        // value of the digits found so far, and the product of the earlier primes, mod p_i
+        unsigned long long t = 0, prod = 1 % pr[i];
+        for (int j = i - 1; j >= 0; --j) t = (t * (pr[j] % pr[i]) + v[j]) % pr[i];
+        for (int j = 0; j < i; ++j) prod = (prod * (pr[j] % pr[i])) % pr[i];
+        const unsigned long long diff = (res[i] + pr[i] - t) % pr[i];
+        v[i] = i == 0 ? res[0] : (diff * powmod_u64(prod, pr[i] - 2, pr[i])) % pr[i];
+    }
+    // S = v_{k-1}; S = S * p_i + v_i (Horner, 32-bit limbs); P = prod p_i
+    unsigned S[RADIC_MAX_PRIMES + 1] = {0}, Pm[RADIC_MAX_PRIMES + 1] = {0};
+    int len = 0, plen = 1;
+    Pm[0] = 1;
+    for (int i = k - 1; i >= 0; --i) {
+        unsigned long long carry = v[i];
+        for (int l = 0; l < len; ++l) {
+            const unsigned long long cur = (unsigned long long)S[l] * pr[i] + carry;
+            S[l] = (unsigned)cur;
+            carry = cur >> 32;
+        }
+        while (carry) {
+            S[len++] = (unsigned)carry;
+            carry >>= 32;
+        }
+    }
+    for (int i = 0; i < k; ++i) {
+        unsigned long long carry = 0;
+        for (int l = 0; l < plen; ++l) {
+            const unsigned long long cur = (unsigned long long)Pm[l] * pr[i] + carry;
+            Pm[l] = (unsigned)cur;
+            carry = cur >> 32;
+        }
+        while (carry) {
+            Pm[plen++] = (unsigned)carry;
+            carry >>= 32;
+        }
+    }
+    // compare 2S with P
+    unsigned S2[RADIC_MAX_PRIMES + 2] = {0};
+    int s2len = len;
+    {
+        unsigned carry = 0;
+        for (int l = 0; l < len; ++l) {
+            S2[l] = (S[l] << 1) | carry;
+            carry = S[l] >> 31;
+        }
+        if (carry) S2[s2len++] = carry;
+    }
+    int cmp = 0;
+    if (s2len != plen) cmp = s2len > plen ? 1 : -1;
+    else
+        for (int l = plen - 1; l >= 0 && cmp == 0; --l)
+            if (S2[l] != Pm[l]) cmp = S2[l] > Pm[l] ? 1 : -1;
+    int sign = len == 0 ? 0 : 1;
+    if (cmp > 0) {   // S > P/2: the value is S - P < 0; magnitude P - S
+        long long borrow = 0;
+        for (int l = 0; l < plen; ++l) {
+            long long cur = (long long)Pm[l] - (l < len ? (long long)S[l] : 0) - borrow;
+            borrow = cur < 0;
+            S[l] = (unsigned)(cur + (borrow ? (1ll << 32) : 0));
+        }
+        len = plen;
+        sign = -1;
+    }
+    while (len > 0 && S[len - 1] == 0) --len;
+    if (len == 0) sign = 0;
+    r.sign = sign;
+    r.mag_len = len;
+    for (int l = 0; l < len; ++l) r.mag[l] = S[l];
+    *out = r;
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t upload_binomials_int(const unsigned long long* host_table) { return upload_binomial_table(host_table); }
+
+hipError_t upload_primes(const unsigned* primes, int count) {
+    double pd[RADIC_MAX_PRIMES] = {0}, pi[RADIC_MAX_PRIMES] = {0};
+    for (int i = 0; i < count && i < RADIC_MAX_PRIMES; ++i) {
+        pd[i] = (double)primes[i];
+        pi[i] = 1.0 / pd[i];
+    }
+    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_prime), pd, sizeof(pd));
+    if (e != hipSuccess) return e;
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_prime_inv), pi, sizeof(pi));
+}
+
+size_t int_header_bytes() { return 256; }
+size_t int_result_offset() { return 256; }
+size_t int_partials_offset() { return 1024; }
+size_t int_workspace_bytes() { return int_partials_offset() + sizeof(double) * (size_t)RADIC_MAX_PRIMES * kMaxGrid; }
+size_t int_result_size() { return sizeof(IntResult); }
+
+int int_lds(int m, int n) {
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: return int_lds_bytes<MM>(n);
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
+#undef RADIC_CASE
+        default: return 1 << 30;
+    }
+}
+
+hipError_t launch_int_bound(const int* A, int m, int n, long long lda, void* ws, int prime_count, hipStream_t s) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_int_bound, dim3(1), dim3(256), 0, s, A, m, n, lda, reinterpret_cast<IntHeader*>(ws),
+                       prime_count);
+    return hipGetLastError();
+}
+
+hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned long long count, int spl,
+                           int grid_x, int n_primes, int block, void* ws, hipStream_t s) {
+    IntJob J{};
+    J.A = A;
+    J.lda = lda;
+    J.m = m;
+    J.n = n;
+    J.count = count;
+    J.spl = spl;
+    J.chunks = (count + spl - 1) / spl;
+    J.grid_x = grid_x;
+    J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
+    J.header = reinterpret_cast<IntHeader*>(ws);
+    const int lds = int_lds(m, n);
+    (void)hipGetLastError();
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: hipLaunchKernelGGL(k_radic_int<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J); break;
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
+#undef RADIC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s) {
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_int_finalize, dim3(1), dim3(64), 0, s,
+                       reinterpret_cast<const double*>(w + int_partials_offset()), grid_x,
+                       reinterpret_cast<const IntHeader*>(w), reinterpret_cast<IntResult*>(w + int_result_offset()));
+    return hipGetLastError();
+}
+
+}  // namespace radic

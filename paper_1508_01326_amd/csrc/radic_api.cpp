@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -19,7 +20,17 @@ hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, i
 hipError_t launch_finalize_float(const Partial* parts, int G, const DetHeader* h, radic_f64_result* out,
                                  unsigned long long count, int use_scale, hipStream_t s);
 hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s);
-hipError_t upload_binomials(const unsigned long long* host_table);
+hipError_t upload_binomials_float(const unsigned long long* host_table);
+hipError_t upload_binomials_int(const unsigned long long* host_table);
+hipError_t upload_primes(const unsigned* primes, int count);
+hipError_t launch_int_bound(const int* A, int m, int n, long long lda, void* ws, int prime_count, hipStream_t s);
+hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned long long count, int spl,
+                           int grid_x, int n_primes, int block, void* ws, hipStream_t s);
+hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s);
+size_t int_workspace_bytes();
+size_t int_result_offset();
+size_t int_result_size();
+int int_lds(int m, int n);
 int float_lds_bytes(int m, int n, int prec, int waves);
 
 constexpr int kBinomRows = RADIC_MAX_N + 1;
@@ -51,9 +62,55 @@ static int device_error(const char* what, hipError_t e) {
     return RADIC_EDEVICE;
 }
 
+// ---------------------------------------------------------------- primes of the exact path
+// Deterministic Miller-Rabin: bases 2, 3, 5, 7 decide every n < 3,215,031,751.
+static bool is_prime_u32(unsigned n) {
+    if (n < 2) return false;
+    for (unsigned d : {2u, 3u, 5u, 7u}) {
+        if (n == d) return true;
+        if (n % d == 0) return false;
+    }
+    unsigned long long d = n - 1;
+    int r = 0;
+    while ((d & 1) == 0) {
+        d >>= 1;
+        ++r;
+    }
+    for (unsigned long long a : {2ull, 3ull, 5ull, 7ull}) {
+        unsigned long long x = 1, b = a % n, e = d;
+        while (e) {
+            if (e & 1) x = x * b % n;
+            b = b * b % n;
+            e >>= 1;
+        }
+        if (x == 1 || x == n - 1) continue;
+        bool comp = true;
+        for (int i = 1; i < r; ++i) {
+            x = x * x % n;
+            if (x == n - 1) {
+                comp = false;
+                break;
+            }
+        }
+        if (comp) return false;
+    }
+    return true;
+}
+
+static std::vector<unsigned> default_primes() {
+    std::vector<unsigned> v;
+    for (unsigned c = 0x7FFFFFFFu; v.size() < (size_t)RADIC_MAX_PRIMES; c -= 2)
+        if (is_prime_u32(c)) v.push_back(c);
+    return v;
+}
+
+static std::vector<unsigned> g_primes = default_primes();
+static int g_prime_version = 1;
+
 // ---------------------------------------------------------------- per-device state
 static std::mutex g_mu;
 static bool g_dev_ready[64];
+static int g_dev_prime_version[64];
 
 static int ensure_device() {
     int dev = 0;
@@ -61,6 +118,11 @@ static int ensure_device() {
     if (ge != hipSuccess) return device_error("hipGetDevice", ge);
     if (dev < 0 || dev >= 64) return RADIC_ENOTSUP;
     std::lock_guard<std::mutex> lk(g_mu);
+    if (g_dev_prime_version[dev] != g_prime_version) {
+        hipError_t pe = upload_primes(g_primes.data(), (int)g_primes.size());
+        if (pe != hipSuccess) return device_error("upload of the prime set", pe);
+        g_dev_prime_version[dev] = g_prime_version;
+    }
     if (g_dev_ready[dev]) return RADIC_OK;
     std::vector<unsigned long long> t((size_t)kBinomRows * kBinomCols, 0);
     for (int x = 0; x < kBinomRows; ++x)
@@ -69,7 +131,8 @@ static int ensure_device() {
             if (host_binomial(x, y, &v) != RADIC_OK) v = ~0ull;   // saturate; never used
             t[(size_t)x * kBinomCols + y] = v;
         }
-    hipError_t ue = upload_binomials(t.data());
+    hipError_t ue = upload_binomials_float(t.data());
+    if (ue == hipSuccess) ue = upload_binomials_int(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
     return RADIC_OK;
@@ -160,6 +223,16 @@ static int zero_result(radic_f64_result* out, hipStream_t s) {
     return e == hipSuccess ? RADIC_OK : device_error("launch of the zero-result kernel", e);
 }
 
+// Each wave keeps its own copy of A in LDS; for wide matrices use fewer waves
+// per workgroup so that the workgroup's LDS stays within kMaxLds.
+static bool fit_lds(int m, int n, int prec, Shape& sh) {
+    while (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) {
+        if (sh.block <= kWave) return false;
+        sh.block -= kWave;
+    }
+    return true;
+}
+
 static int grid_for(unsigned long long chunks, int block) {
     const unsigned long long wave_chunks = (chunks + kWave - 1) / kWave;
     const unsigned long long wpb = (unsigned long long)(block / kWave);
@@ -189,7 +262,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     }
     if (count == 0) return zero_result(dOut, stream);
     Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
-    if (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) return RADIC_ENOTSUP;
+    if (!fit_lds(m, n, prec, sh)) return RADIC_ENOTSUP;
 
     unsigned char* ws = static_cast<unsigned char*>(dWork);
     FloatJob J{};
@@ -247,6 +320,9 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch) {
         case RADIC_WS_DET:
             if (m < 1 || n < 1) return 0;
             return det_workspace_bytes();
+        case RADIC_WS_INT:
+            if (m < 1 || n < 1) return 0;
+            return int_workspace_bytes();
         default:
             (void)batch;
             return 0;
@@ -277,7 +353,7 @@ int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uin
     if (count > total - q_begin) count = total - q_begin;
     if (count > (1ull << 31)) return RADIC_EOVERFLOW;
     Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
-    if (float_lds_bytes(m, n, prec, sh.block / kWave) > kMaxLds) return RADIC_ENOTSUP;
+    if (!fit_lds(m, n, prec, sh)) return RADIC_ENOTSUP;
     FloatJob J{};
     J.A = dA;
     J.lda = lda;
@@ -298,8 +374,57 @@ int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uin
     return e == hipSuccess ? RADIC_OK : device_error("launch of the export kernel", e);
 }
 
-int radic_det_int_exact(const int32_t*, int, int, int64_t, uint32_t*, int, int*, int*, void*, size_t, hipStream_t) {
-    return RADIC_ENOTSUP;
+int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* hMag, int mag_capacity,
+                        int* hMagLen, int* hSign, void* dWork, size_t work_bytes, hipStream_t stream) {
+    if (!dA || !hMag || !hMagLen || !hSign || mag_capacity < 0 || m < 1 || n < 1 || lda < n) return RADIC_EINVAL;
+    *hMagLen = 0;
+    *hSign = 0;
+    if (m > n) return RADIC_OK;   // Definition 3: zero
+    if (m > RADIC_MAX_M || n > RADIC_MAX_N) return RADIC_ENOTSUP;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
+    int rc = check_workspace(dWork, work_bytes, int_workspace_bytes());
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    int prime_count;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        prime_count = (int)g_primes.size();
+    }
+    Shape sh = pick_shape(RADIC_WS_INT, 0, m, n);
+    if (int_lds(m, n) > kMaxLds) return RADIC_ENOTSUP;
+    // 1. bound -> number of primes (read back: this entry point is synchronous)
+    hipError_t e = launch_int_bound(dA, m, n, lda, dWork, prime_count, stream);
+    if (e != hipSuccess) return device_error("launch of the bound kernel", e);
+    int hdr[2] = {0, 0};
+    e = hipMemcpyAsync(hdr, dWork, sizeof(hdr), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error("read-back of the prime count", e);
+    if (hdr[1] != RADIC_OK) return RADIC_EOVERFLOW;
+    const int k = hdr[0];
+    // 2. residue sums per (workgroup, prime), 3. CRT
+    const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
+    const int grid = grid_for(chunks, sh.block);
+    {
+        ProfScope ps(stream);
+        e = launch_int_main(dA, m, n, lda, total, sh.spl, grid, k, sh.block, dWork, stream);
+    }
+    if (e != hipSuccess) return device_error("launch of the modular kernel", e);
+    e = launch_int_finalize(grid, dWork, stream);
+    if (e != hipSuccess) return device_error("launch of the CRT kernel", e);
+    std::vector<unsigned char> res(int_result_size());
+    e = hipMemcpyAsync(res.data(), static_cast<unsigned char*>(dWork) + int_result_offset(), res.size(),
+                       hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error("read-back of the exact result", e);
+    int fields[4];
+    std::memcpy(fields, res.data(), sizeof(fields));   // status, sign, mag_len, n_primes
+    if (fields[0] != RADIC_OK) return fields[0];
+    *hMagLen = fields[2];
+    if (fields[2] > mag_capacity) return RADIC_EOVERFLOW;
+    std::memcpy(hMag, res.data() + sizeof(fields), sizeof(uint32_t) * (size_t)fields[2]);
+    *hSign = fields[1];
+    return RADIC_OK;
 }
 
 int radic_det_batched(const radic_matrix_desc*, int, const double*, const int32_t*, int, radic_batch_result*,
@@ -410,6 +535,32 @@ int radic_host_unrank(int m, int n, uint64_t q, int* hCols) {
     return RADIC_OK;
 }
 
-int radic_host_prime(int, uint32_t*) { return RADIC_ENOTSUP; }
+int radic_host_prime(int i, uint32_t* hPrime) {
+    if (!hPrime) return RADIC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (i < 0 || i >= (int)g_primes.size()) return RADIC_EINVAL;
+    *hPrime = g_primes[(size_t)i];
+    return RADIC_OK;
+}
+
+int radic_set_prime_set(const uint32_t* hPrimes, int count) {
+    if (count < 0 || count > RADIC_MAX_PRIMES || (count > 0 && !hPrimes)) return RADIC_EINVAL;
+    std::vector<unsigned> v;
+    if (count == 0) {
+        v = default_primes();
+    } else {
+        for (int i = 0; i < count; ++i) {
+            const unsigned p = hPrimes[i];
+            if (p < 3 || p >= 0x80000000u || !is_prime_u32(p)) return RADIC_EINVAL;
+            for (unsigned q : v)
+                if (q == p) return RADIC_EINVAL;
+            v.push_back(p);
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_primes = v;
+    ++g_prime_version;
+    return RADIC_OK;
+}
 
 }  // extern "C"

@@ -118,6 +118,10 @@ __device__ __forceinline__ double recip(double x) {
 }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Fused multiply-add in the operand type (the generic builtin is double-only).
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // ---------------------------------------------------------------- host helpers
 int host_binomial(int a, int b, unsigned long long* out);   // 0 or RADIC_EOVERFLOW
 

@@ -104,3 +104,62 @@ def test_launch_and_tau_setters_validate():
     assert L.radic_set_fallback_tau(float("nan")) == radic.RADIC_EINVAL
     assert L.radic_set_fallback_tau(-1.0) == radic.RADIC_EINVAL
     assert L.radic_set_fallback_tau(1.0 / 1024) == radic.RADIC_OK
+
+
+def _is_prime(n):
+    if n < 2:
+        return False
+    i = 2
+    while i * i <= n:
+        if n % i == 0:
+            return False
+        i += 1
+    return True
+
+
+def test_default_prime_set():
+    primes = [radic.host_prime(i) for i in range(radic.binding.RADIC_MAX_PRIMES)]
+    assert primes == sorted(primes, reverse=True)
+    assert len(set(primes)) == len(primes)
+    assert all(p < 2 ** 31 for p in primes)
+    assert all(_is_prime(p) for p in primes)      # trial division, independent of the library's test
+    # they are the largest primes below 2^31: no prime is skipped in between
+    lo = primes[-1]
+    expect = [c for c in range(2 ** 31 - 1, lo - 1, -2) if _is_prime(c)]
+    assert primes == expect
+    with pytest.raises(radic.RadicError):
+        radic.host_prime(radic.binding.RADIC_MAX_PRIMES)
+
+
+def test_prime_set_validation():
+    L = radic.lib()
+    arr = (ctypes.c_uint32 * 3)(7, 11, 15)        # 15 is composite
+    assert L.radic_set_prime_set(arr, 3) == radic.RADIC_EINVAL
+    arr = (ctypes.c_uint32 * 2)(7, 7)             # duplicate
+    assert L.radic_set_prime_set(arr, 2) == radic.RADIC_EINVAL
+    arr = (ctypes.c_uint32 * 1)(2)                # even prime is not allowed
+    assert L.radic_set_prime_set(arr, 1) == radic.RADIC_EINVAL
+    arr = (ctypes.c_uint32 * 2)(13, 7)
+    assert L.radic_set_prime_set(arr, 2) == radic.RADIC_OK
+    assert radic.host_prime(0) == 13 and radic.host_prime(1) == 7
+    assert L.radic_set_prime_set(arr, 0) == radic.RADIC_OK   # back to the default set
+    assert radic.host_prime(0) == 2 ** 31 - 1
+
+
+def test_int_validation_without_device():
+    L = radic.lib()
+    nul = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(0x1000)
+    mag = (ctypes.c_uint32 * 8)()
+    ln, sg = ctypes.c_int(7), ctypes.c_int(7)
+    assert L.radic_det_int_exact(nul, 2, 3, 3, mag, 8, ctypes.byref(ln), ctypes.byref(sg), fake, 1 << 24,
+                                 nul) == radic.RADIC_EINVAL
+    assert L.radic_det_int_exact(fake, 2, 3, 2, mag, 8, ctypes.byref(ln), ctypes.byref(sg), fake, 1 << 24,
+                                 nul) == radic.RADIC_EINVAL
+    # m > n is zero by Definition 3, decided on the host
+    assert L.radic_det_int_exact(fake, 4, 3, 3, mag, 8, ctypes.byref(ln), ctypes.byref(sg), fake, 1 << 24,
+                                 nul) == radic.RADIC_OK
+    assert ln.value == 0 and sg.value == 0
+    assert L.radic_det_int_exact(fake, 13, 20, 20, mag, 8, ctypes.byref(ln), ctypes.byref(sg), fake, 1 << 24,
+                                 nul) == radic.RADIC_ENOTSUP
+    assert L.radic_workspace_bytes(radic.RADIC_WS_INT, 6, 40, 0) > 0

@@ -1,0 +1,103 @@
+"""GPU parity of the exact integer path against the BigInt oracle (bit-exact)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import exact
+import workloads
+from tests.parity import to_device
+
+pytestmark = pytest.mark.gpu
+
+radic = pytest.importorskip("paper_1508_01326_amd")
+
+
+@pytest.fixture(autouse=True)
+def _defaults():
+    radic.set_prime_set([])
+    radic.set_launch(0, 0)
+    yield
+    radic.set_prime_set([])
+    radic.set_launch(0, 0)
+
+
+def run_int(A, what):
+    print(f"[case] int {what} shape={A.shape}", flush=True)
+    return radic.radic_det_int_exact(to_device(np.ascontiguousarray(A, dtype=np.int32)))
+
+
+SHAPES = [(1, 1), (1, 9), (2, 2), (2, 40), (3, 11), (4, 13), (5, 14), (6, 12), (7, 15), (8, 16), (9, 14),
+          (10, 13), (11, 14), (12, 14)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_random_int_shapes(shape):
+    m, n = shape
+    A = workloads.random_int(m, n, seed=m * 100 + n, lo=-50, hi=50)
+    assert run_int(A, f"random {shape}") == oracle.radic_int(A)
+
+
+def test_workload3_full():
+    A = workloads.single_matrix(3)    # 6 x 40, entries in [-9, 9], C(40,6) = 3838380 minors
+    ref = oracle.radic_int(A)
+    assert ref == exact.radic_subset_dp(A)
+    assert run_int(A, "workload3 6x40") == ref
+
+
+def test_extreme_entries():
+    rng = np.random.default_rng(7)
+    A = rng.integers(-2 ** 31, 2 ** 31, size=(7, 11), dtype=np.int64).astype(np.int32)
+    A[0, 0] = -2 ** 31
+    A[3, 5] = 2 ** 31 - 1
+    got = run_int(A, "int32 extremes")
+    assert got == oracle.radic_int(A) == exact.radic_subset_dp(A)
+    assert abs(got).bit_length() > 200     # needs many primes
+
+
+def test_zero_pivots_and_structure():
+    # leading zero columns force exchanges; equal rows give exactly zero
+    A = np.array([[0, 0, 1, 2, 3, 0], [0, 1, 0, 4, 5, 0], [1, 0, 0, 6, 7, 0]], dtype=np.int32)
+    assert run_int(A, "leading zeros") == oracle.radic_int(A)
+    B = workloads.random_int(5, 12, seed=3)
+    B[4] = B[1]
+    assert run_int(B, "equal rows") == 0
+    Z = np.zeros((4, 9), dtype=np.int32)
+    assert run_int(Z, "zero matrix") == 0
+    assert run_int(np.ones((5, 4), dtype=np.int32), "m > n") == 0
+
+
+def test_tiny_prime_set():
+    # small primes make pivots vanish mod p and need many residues; the CRT must still be exact
+    A = workloads.random_int(4, 10, seed=44, lo=-3, hi=3)
+    ref = oracle.radic_int(A)
+    radic.set_prime_set([3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37, 41, 43, 47, 53, 59, 61, 67, 71, 73, 79, 83, 89, 97])
+    assert run_int(A, "tiny primes") == ref
+
+
+def test_launch_shapes_int():
+    A = workloads.random_int(5, 17, seed=5)
+    ref = oracle.radic_int(A)
+    for spl, block in [(1, 64), (7, 128), (32, 256)]:
+        radic.set_launch(spl, block)
+        assert run_int(A, f"launch {spl},{block}") == ref
+
+
+def test_capacity_too_small():
+    import ctypes
+    A = workloads.random_int(6, 14, seed=9, lo=-1000, hi=1000)
+    ref = oracle.radic_int(A)
+    dA = to_device(A)
+    work = radic.workspace(radic.RADIC_WS_INT, 6, 14, device=dA.device)
+    mag = (ctypes.c_uint32 * 1)()
+    ln, sg = ctypes.c_int(0), ctypes.c_int(0)
+    import torch
+    rc = radic.lib().radic_det_int_exact(ctypes.c_void_p(dA.data_ptr()), 6, 14, 14, mag, 1, ctypes.byref(ln),
+                                         ctypes.byref(sg), ctypes.c_void_p(work.data_ptr()), work.numel(),
+                                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    need = (abs(ref).bit_length() + 31) // 32
+    if need > 1:
+        assert rc == radic.RADIC_EOVERFLOW and ln.value == need
+    else:
+        assert rc == radic.RADIC_OK
