@@ -292,3 +292,82 @@ def host_prime(i):
     p = ctypes.c_uint32(0)
     _check(lib().radic_host_prime(int(i), ctypes.byref(p)), "radic_host_prime")
     return int(p.value)
+
+
+# ------------------------------------------------------------------ batched
+class Batch:
+    """Device buffers for radic_det_batched: entry pools, descriptors, results and
+    workspace, built from a list of 2-D numpy arrays (float64 or int32)."""
+
+    def __init__(self, matrices, device="cuda"):
+        torch = _torch()
+        f64, i32, desc = [], [], np.zeros(len(matrices), dtype=DESC_DTYPE)
+        foff = ioff = 0
+        for b, A in enumerate(matrices):
+            A = np.asarray(A)
+            m, n = A.shape
+            if A.dtype == np.float64:
+                desc[b] = (m, n, 0, 0, foff, n)
+                f64.append(np.ascontiguousarray(A).ravel())
+                foff += A.size
+            elif A.dtype == np.int32:
+                desc[b] = (m, n, 1, 0, ioff, n)
+                i32.append(np.ascontiguousarray(A).ravel())
+                ioff += A.size
+            else:
+                raise ValueError("matrices must be float64 or int32")
+        self.batch = len(matrices)
+        self.desc_host = desc
+        self.desc = torch.from_numpy(desc.view(np.uint8).copy()).to(device)
+        self.f64 = torch.from_numpy(np.concatenate(f64) if f64 else np.zeros(1)).to(device)
+        self.i32 = torch.from_numpy(np.concatenate(i32) if i32 else np.zeros(1, np.int32)).to(device)
+        self.out = torch.zeros(self.batch * BATCH_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device)
+        self.work = workspace(RADIC_WS_BATCHED, batch=self.batch, device=device)
+
+    def args(self, precision):
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        return (ctypes.c_void_p(self.desc.data_ptr()), self.batch, ctypes.c_void_p(self.f64.data_ptr()),
+                ctypes.c_void_p(self.i32.data_ptr()), prec, ctypes.c_void_p(self.out.data_ptr()),
+                ctypes.c_void_p(self.work.data_ptr()), self.work.numel())
+
+    def results(self):
+        raw = self.out.cpu().numpy().tobytes()
+        rows = np.frombuffer(raw, dtype=BATCH_RESULT_DTYPE)
+        res = []
+        for r in rows:
+            d = {k: r[k].item() for k in ("value", "hi", "lo", "abs_sum", "n_subsets", "n_fallback", "status",
+                                          "sign", "mag_len", "n_primes")}
+            v = 0
+            for l in reversed(range(int(r["mag_len"]))):
+                v = (v << 32) | int(r["mag"][l])
+            d["exact"] = -v if r["sign"] < 0 else v
+            res.append(d)
+        return res
+
+
+def radic_det_batched(batch, precision="fp64", stream=None, sync=True):
+    """Run radic_det_batched on a Batch; returns the per-matrix result dicts."""
+    torch = _torch()
+    rc = lib().radic_det_batched(*batch.args(precision), _stream_handle(stream))
+    _check(rc, "radic_det_batched")
+    if not sync:
+        return None
+    torch.cuda.synchronize()
+    return batch.results()
+
+
+class BatchGraph:
+    """A HIP graph holding one radic_det_batched call (radic_batched_graph_create)."""
+
+    def __init__(self, batch, precision="fp64"):
+        self.handle = ctypes.c_void_p(0)
+        rc = lib().radic_batched_graph_create(*batch.args(precision), ctypes.byref(self.handle))
+        _check(rc, "radic_batched_graph_create")
+
+    def launch(self, stream=None):
+        _check(lib().radic_graph_launch(self.handle, _stream_handle(stream)), "radic_graph_launch")
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().radic_graph_destroy(self.handle), "radic_graph_destroy")
+            self.handle = ctypes.c_void_p(0)

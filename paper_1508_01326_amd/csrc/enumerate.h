@@ -39,12 +39,13 @@ __device__ void stage_binomials(unsigned long long* bt, int n) {
 // value c there number C(n-1-c, M-1-k) (0-based c); step c to the right while q
 // can pay for them.
 template <int M>
-__device__ __forceinline__ void unrank(unsigned long long q, int n, const unsigned long long* bt, int (&col)[M]) {
+__device__ __forceinline__ void unrank_strided(unsigned long long q, int n, const unsigned long long* bt, int stride,
+                                               int (&col)[M]) {
     int c = 0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
         for (;;) {
-            unsigned long long w = bt[(n - 1 - c) * M + (M - 1 - k)];
+            unsigned long long w = bt[(n - 1 - c) * stride + (M - 1 - k)];
             if (q < w) break;
             q -= w;
             ++c;
@@ -52,6 +53,12 @@ __device__ __forceinline__ void unrank(unsigned long long q, int n, const unsign
         col[k] = c;
         ++c;
     }
+}
+
+// Same, reading the LDS slice bt[x*M + y] = C(x, y).
+template <int M>
+__device__ __forceinline__ void unrank(unsigned long long q, int n, const unsigned long long* bt, int (&col)[M]) {
+    unrank_strided<M>(q, n, bt, M, col);
 }
 
 // Dictionary successor (Section 5): the rightmost place still below its maximum

@@ -1,0 +1,594 @@
+// Batched Radic determinants: many matrices of mixed shape and type in
+// persistent kernels fed by global work queues.
+//
+// The rank space [0, C(n_b, m_b)) of every matrix b is cut into chunks (the
+// granularity scheme of Section 5 applied to the whole batch).  A setup kernel
+// validates the descriptors and sizes the chunks, a one-workgroup scan turns the
+// per-matrix chunk counts into queue prefixes, and resident waves of two
+// persistent kernels (float matrices; exact int32 matrices) take chunk indices
+// from a global atomic counter until the queue is empty.  A wave that takes a
+// chunk of a matrix other than the one it holds stages that matrix in its own
+// LDS region, then runs the same per-lane enumeration and LU (or modular
+// elimination) as the single-matrix kernels.  Float chunks write their partial
+// sums to per-(matrix, chunk) slots, which a final kernel reduces in chunk
+// order, so float results do not depend on the order in which waves took chunks;
+// exact chunks add residues into per-(matrix, prime) 64-bit sums, which is exact
+// and order independent.  No kernel allocates or clears memory through the
+// runtime, so the whole sequence can be captured in a HIP graph.
+#include <type_traits>
+
+#include "lu_float.h"
+#include "modp.h"
+
+namespace radic {
+
+constexpr int kBatchMaxN = 64;           // widest matrix a wave stages in LDS
+constexpr int kBatchWaves = 4;           // waves per workgroup of the persistent kernels
+
+struct BatchMeta {
+    unsigned long long total;    // C(n, m)
+    unsigned long long chunk;    // ranks per chunk (a multiple of 64)
+    unsigned long long nchunks;
+    int status;                  // per-matrix radic status
+    int kind;                    // 0 float, 1 exact, -1 no work (error or m > n)
+    int n_primes;
+    int scale_exp;               // FP32_BULK: sum of the row exponents
+};
+
+// Work classes: (kind, m), kind 0 float / 1 exact, m = 1..RADIC_MAX_M.  Each
+// class has its own queue and its own persistent kernel, compiled for that m
+// only, so a kernel's register allocation is that of its own minor size.
+constexpr int kClasses = 2 * RADIC_MAX_M;
+__host__ __device__ inline int class_of(int kind, int m) { return kind * RADIC_MAX_M + (m - 1); }
+
+struct BatchHeader {
+    unsigned long long chunks[kClasses];   // queue length per class
+    unsigned int queue[kClasses];          // next chunk index per class
+};
+
+static_assert(sizeof(BatchHeader) == 8 * kClasses + 4 * kClasses, "batch header layout");
+
+struct BatchJob {
+    const radic_matrix_desc* desc;
+    int batch;
+    const double* f64;
+    const int* i32;
+    int prec;
+    double tau;
+    int spl_float;
+    int spl_int;
+    int prime_count;
+    radic_batch_result* out;
+    BatchHeader* header;
+    BatchMeta* meta;
+    unsigned long long* prefix;         // [kClasses][batch + 1]
+    Partial* partials;                  // [batch][kBatchChunksPerMatrix]
+    unsigned long long* residues;       // [batch][RADIC_MAX_PRIMES]
+};
+
+// Workspace layout (offsets in bytes, all 256-byte aligned)
+__host__ __device__ inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+__host__ __device__ inline size_t off_meta() { return align256(sizeof(BatchHeader)); }
+__host__ __device__ inline size_t off_prefix(int batch) { return off_meta() + align256(sizeof(BatchMeta) * batch); }
+__host__ __device__ inline size_t off_partials(int batch) {
+    return off_prefix(batch) + align256(8 * (size_t)kClasses * (batch + 1));
+}
+__host__ __device__ inline size_t off_residues(int batch) {
+    return off_partials(batch) + align256(sizeof(Partial) * (size_t)kBatchChunksPerMatrix * batch);
+}
+__host__ __device__ inline size_t batch_ws_bytes(int batch) {
+    return off_residues(batch) + align256(8 * (size_t)RADIC_MAX_PRIMES * batch);
+}
+
+// ---------------------------------------------------------------- setup
+__global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= J.batch) return;
+    const radic_matrix_desc d = J.desc[b];
+    BatchMeta mt{};
+    mt.kind = -1;
+    mt.status = RADIC_OK;
+    for (int i = 0; i < RADIC_MAX_PRIMES; ++i) J.residues[(size_t)b * RADIC_MAX_PRIMES + i] = 0ull;
+    const bool bad_dtype = d.dtype != 0 && d.dtype != 1;
+    const bool no_pool = (d.dtype == 0 && !J.f64) || (d.dtype == 1 && !J.i32);
+    if (d.m < 1 || d.n < 1 || d.lda < d.n || d.offset < 0 || bad_dtype || no_pool) {
+        mt.status = RADIC_EINVAL;
+    } else if (d.m > d.n) {
+        mt.status = RADIC_OK;   // Definition 3: zero
+    } else if (d.m > RADIC_MAX_M || d.n > kBatchMaxN) {
+        mt.status = RADIC_ENOTSUP;
+    } else {
+        const unsigned long long total = g_binom[d.n * kBinomCols + d.m];
+        if (total >= (1ull << 63)) {
+            mt.status = RADIC_EOVERFLOW;
+        } else if (d.dtype == 0) {
+            mt.kind = 0;
+            mt.total = total;
+            const unsigned long long minc = 64ull * (unsigned long long)J.spl_float;
+            unsigned long long c = (total + kBatchChunksPerMatrix - 1) / kBatchChunksPerMatrix;
+            c = (c + 63) & ~63ull;
+            mt.chunk = c > minc ? c : minc;
+            mt.nchunks = (total + mt.chunk - 1) / mt.chunk;
+            const double* A = J.f64 + d.offset;
+            int se = 0, bad = 0;
+            for (int i = 0; i < d.m; ++i) {
+                double mx = 0.0;
+                for (int j = 0; j < d.n; ++j) {
+                    const double v = A[(long long)i * d.lda + j];
+                    bad |= !isfinite(v);
+                    mx = fmax(mx, fabs(v));
+                }
+                int e = 0;
+                if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
+                se += e;
+            }
+            mt.scale_exp = J.prec == RADIC_FP32_BULK ? se : 0;
+            if (bad) {
+                mt.status = RADIC_ENONFINITE;
+                mt.kind = -1;
+            }
+        } else {
+            // exact: primes for the bound e_m(column norms) (Hadamard per minor)
+            const int* A = J.i32 + d.offset;
+            double e[RADIC_MAX_M + 1];
+            e[0] = 1.0;
+            for (int k = 1; k <= d.m; ++k) e[k] = 0.0;
+            for (int j = 0; j < d.n; ++j) {
+                double s = 0.0;
+                for (int i = 0; i < d.m; ++i) {
+                    const double a = (double)A[(long long)i * d.lda + j];
+                    s = __builtin_fma(a, a, s);
+                }
+                const double x = sqrt(s) * (1.0 + 1e-12);
+                for (int k = d.m; k >= 1; --k) e[k] = __builtin_fma(x, e[k - 1], e[k]);
+            }
+            const double need = log2(e[d.m] * (1.0 + 1e-9) + 1.0) + 1.0 + 1e-6;
+            double have = 0.0;
+            int k = 0;
+            while (k < J.prime_count && have <= need) have += log2(g_prime[k++]);
+            if (have <= need || k > RADIC_MAX_PRIMES) {
+                mt.status = RADIC_EOVERFLOW;
+            } else {
+                mt.kind = 1;
+                mt.total = total;
+                mt.n_primes = k;
+                mt.chunk = 64ull * (unsigned long long)J.spl_int;
+                mt.nchunks = (total + mt.chunk - 1) / mt.chunk;
+            }
+        }
+    }
+    J.meta[b] = mt;
+}
+
+// One workgroup per class: prefix sums of the class's chunk counts in matrix
+// order, and the class queue reset.
+__global__ __launch_bounds__(1024) void k_batch_scan(BatchJob J) {
+    __shared__ unsigned long long sf[1024];
+    const int cls = blockIdx.x;
+    unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
+    const int per = (J.batch + blockDim.x - 1) / blockDim.x;
+    const int b0 = threadIdx.x * per;
+    auto count = [&](int b) -> unsigned long long {
+        const BatchMeta& mt = J.meta[b];
+        return (mt.kind >= 0 && class_of(mt.kind, J.desc[b].m) == cls) ? mt.nchunks : 0ull;
+    };
+    unsigned long long f = 0;
+    for (int b = b0; b < b0 + per && b < J.batch; ++b) f += count(b);
+    sf[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {   // inclusive Hillis-Steele scan
+        const unsigned long long a = threadIdx.x >= (unsigned)off ? sf[threadIdx.x - off] : 0ull;
+        __syncthreads();
+        sf[threadIdx.x] += a;
+        __syncthreads();
+    }
+    f = threadIdx.x ? sf[threadIdx.x - 1] : 0ull;
+    for (int b = b0; b < b0 + per && b < J.batch; ++b) {
+        prefix[b] = f;
+        f += count(b);
+    }
+    if (threadIdx.x == blockDim.x - 1) {
+        prefix[J.batch] = sf[blockDim.x - 1];
+        J.header->chunks[cls] = sf[blockDim.x - 1];
+        J.header->queue[cls] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- queue helpers
+__device__ __forceinline__ unsigned long long take_chunk(unsigned int* queue, int lane) {
+    unsigned int g = 0;
+    if (lane == 0) g = atomicAdd(queue, 1u);
+    return (unsigned long long)__shfl(g, 0, kWave);
+}
+
+// matrix b with prefix[b] <= g < prefix[b + 1] (prefix nondecreasing, prefix[0] = 0)
+__device__ __forceinline__ int find_matrix(const unsigned long long* prefix, int batch, unsigned long long g) {
+    int lo = 0, hi = batch;   // invariant: prefix[lo] <= g < prefix[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------- float chunks
+// Per-wave LDS of a float class: the double copy of the staged matrix, and for
+// FP32_BULK the float copy (with the column-scale slot), the fallback queue and
+// the scratch of the wave-cooperative double refactorisation.
+template <int M, bool F32> struct FloatWaveLds {
+    double cd[kBatchMaxN * Layout<M>::st64];
+    float cf[F32 ? kBatchMaxN * Layout<M>::st32 : 1];
+    unsigned queue[F32 ? 4 * kFallbackCap : 1];
+    double W[F32 ? M * M : 1];
+    int rowexp[M];
+};
+
+template <int M, bool F32>
+__device__ void stage_float(const BatchJob& J, const radic_matrix_desc& d, FloatWaveLds<M, F32>& L, int lane) {
+    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    const double* A = J.f64 + d.offset;
+    const int n = d.n;
+    if (F32 && lane < M) {   // exponent of row `lane`'s maximum, max |a_ij| = f 2^e with f in [0.5, 1)
+        double mx = 0.0;
+        for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(A[(long long)lane * d.lda + j]));
+        int e_row = 0;
+        if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e_row);
+        L.rowexp[lane] = e_row;
+    }
+    wave_lds_sync();
+    for (int e = lane; e < M * n; e += kWave) {
+        const int i = e / n, j = e - i * n;
+        double v = A[(long long)i * d.lda + j];
+        if (F32) v = ldexp(v, -L.rowexp[i]);
+        L.cd[j * ST64 + i] = v;
+        if (F32) L.cf[j * ST32 + i] = (float)v;
+    }
+    wave_lds_sync();
+    if (F32) {
+        for (int j = lane; j < n; j += kWave) {
+            float s = 0.f;
+#pragma unroll
+            for (int i = 0; i < M; ++i) s = fmaxf(s, fabsf(L.cf[j * ST32 + i]));
+            L.cf[j * ST32 + M] = s > 0.f ? 1.0f / s : 0.f;
+        }
+        wave_lds_sync();
+    }
+}
+
+template <int M>
+__device__ void flush_batch_fallback(const double* cd, unsigned* queue, int count, double* W, int lane, double& hi,
+                                     double& lo, double& ab) {
+    for (int e = 0; e < count; ++e) {
+        int c[M];
+        unpack_cols<M>(queue + 4 * e, c);
+        const double d = coop_det_f64<M>(cd, c, W, lane);
+        const double term = radic_sign_odd<M>(c) ? -d : d;
+        if (lane == 0) {
+            double s, err;
+            two_sum(hi, term, s, err);
+            hi = s;
+            lo += err;
+            ab += fabs(d);
+        }
+        wave_lds_sync();
+    }
+}
+
+template <int M, bool F32>
+__device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const BatchMeta& mt,
+                            unsigned long long c, FloatWaveLds<M, F32>& L, int lane, bool restage, Partial& out) {
+    using T = typename std::conditional<F32, float, double>::type;
+    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    if (restage) stage_float<M, F32>(J, d, L, lane);
+    const int n = d.n;
+    const T* colbase = F32 ? reinterpret_cast<const T*>(L.cf) : reinterpret_cast<const T*>(L.cd);
+    const int colstride = F32 ? ST32 : ST64;
+    const T tau = (T)J.tau;
+    const unsigned long long sub = mt.chunk / kWave;          // ranks per lane
+    const unsigned long long q0 = c * mt.chunk + (unsigned long long)lane * sub;
+    const int cnt = q0 < mt.total ? (int)((mt.total - q0) < sub ? (mt.total - q0) : sub) : 0;
+    int col[M];
+    unrank_strided<M>(q0 < mt.total ? q0 : mt.total - 1, n, g_binom, kBinomCols, col);
+    unsigned long long perm = 0;   // natural row order (no wave copy in the batched kernel)
+    int perm_odd = 0;
+#pragma unroll
+    for (int r = 0; r < M; ++r) perm |= (unsigned long long)r << (4 * r);
+    double hi = 0.0, lo = 0.0, ab = 0.0;
+    unsigned long long nfb = 0;
+    int qcount = 0;
+    for (unsigned long long s = 0; s < sub; ++s) {
+        const bool valid = s < (unsigned long long)cnt;
+        T a[M][M];
+        gather<M, T>(a, colbase, colstride, col);
+        T sc[M];
+        if (F32) {
+#pragma unroll
+            for (int j = 0; j < M; ++j) sc[j] = colbase[col[j] * colstride + M];
+        }
+        bool neg = radic_sign_odd<M>(col);
+        bool flag = false;
+        const T det = lu_det<M, T, F32>(a, neg, flag, sc, tau, perm, perm_odd);
+        perm_odd = 0;   // rows are always gathered in their natural order here
+#pragma unroll
+        for (int r = 0; r < M; ++r) perm = (perm & ~(15ull << (4 * r))) | ((unsigned long long)r << (4 * r));
+        flag = flag && valid;
+        if (valid && !flag) {
+            const double dd = (double)det;
+            const double term = neg ? -dd : dd;
+            double sum, err;
+            two_sum(hi, term, sum, err);
+            hi = sum;
+            lo += err;
+            ab += fabs(dd);
+        }
+        if (F32) {
+            const unsigned long long fm = __ballot(flag);
+            if (fm) {
+                if (flag) {
+                    const int pos = qcount + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
+                    unsigned w[3];
+                    pack_cols<M>(col, w);
+                    L.queue[4 * pos + 0] = w[0];
+                    L.queue[4 * pos + 1] = w[1];
+                    L.queue[4 * pos + 2] = w[2];
+                    L.queue[4 * pos + 3] = 0u;
+                    nfb += 1;
+                }
+                qcount += __popcll(fm);
+                if (qcount > kFallbackCap - kWave) {
+                    wave_lds_sync();
+                    flush_batch_fallback<M>(L.cd, L.queue, qcount, L.W, lane, hi, lo, ab);
+                    qcount = 0;
+                }
+            }
+        }
+        successor<M>(col, n);
+    }
+    if (F32 && qcount > 0) {
+        wave_lds_sync();
+        flush_batch_fallback<M>(L.cd, L.queue, qcount, L.W, lane, hi, lo, ab);
+    }
+    wave_reduce_partial(hi, lo, ab, nfb);
+    out = Partial{hi, lo, ab, nfb};
+}
+
+template <bool F32, int M>
+__global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J) {
+    __shared__ FloatWaveLds<M, F32> lds[kBatchWaves];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    FloatWaveLds<M, F32>& L = lds[wave];
+    constexpr int cls = M - 1;   // class_of(0, M)
+    const unsigned long long total = J.header->chunks[cls];
+    const unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
+    int staged = -1;
+    for (;;) {
+        const unsigned long long g = take_chunk(&J.header->queue[cls], lane);
+        if (g >= total) break;
+        const int b = find_matrix(prefix, J.batch, g);
+        const unsigned long long c = g - prefix[b];
+        const radic_matrix_desc d = J.desc[b];
+        const BatchMeta mt = J.meta[b];
+        const bool restage = b != staged;
+        staged = b;
+        Partial p{};
+        float_chunk<M, F32>(J, d, mt, c, L, lane, restage, p);
+        if (lane == 0) J.partials[(size_t)b * kBatchChunksPerMatrix + c] = p;
+    }
+}
+
+// ---------------------------------------------------------------- exact chunks
+template <int M> struct IntWaveLds {
+    double cr[kBatchMaxN * IntLayout<M>::st];
+};
+
+template <int M>
+__device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const BatchMeta& mt, unsigned long long c,
+                          int b, IntWaveLds<M>& L, int lane, bool restage) {
+    constexpr int ST = IntLayout<M>::st;
+    const int n = d.n;
+    (void)restage;   // residues are restaged per prime
+    const int* A = J.i32 + d.offset;
+    const unsigned long long sub = mt.chunk / kWave;
+    const unsigned long long q0 = c * mt.chunk + (unsigned long long)lane * sub;
+    const int cnt = q0 < mt.total ? (int)((mt.total - q0) < sub ? (mt.total - q0) : sub) : 0;
+    for (int pi = 0; pi < mt.n_primes; ++pi) {
+        const double p = g_prime[pi], pinv = g_prime_inv[pi];
+        wave_lds_sync();
+        for (int e = lane; e < M * n; e += kWave) {
+            const int i = e / n, j = e - i * n;
+            const double v = (double)A[(long long)i * d.lda + j];
+            const double q = __builtin_floor(v * pinv);
+            L.cr[j * ST + i] = mod_fix(__builtin_fma(-q, p, v), p);
+        }
+        wave_lds_sync();
+        int col[M];
+        unrank_strided<M>(q0 < mt.total ? q0 : mt.total - 1, n, g_binom, kBinomCols, col);
+        double num = 0.0, den = 1.0;
+        for (unsigned long long s = 0; s < sub; ++s) {
+            double a[M][M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double* src = L.cr + col[j] * ST;
+#pragma unroll
+                for (int i = 0; i + 1 < M; i += 2) {
+                    const double2 v = *reinterpret_cast<const double2*>(src + i);
+                    a[i][j] = v.x;
+                    a[i + 1][j] = v.y;
+                }
+                if (M & 1) a[M - 1][j] = src[M - 1];
+            }
+            double N = 1.0, P = 1.0, D = 1.0;
+            bool zero = false;
+            bool neg = radic_sign_odd<M>(col);
+            elim_steps_mod<M, 0>(a, p, pinv, N, P, D, zero, neg);
+            if (s < (unsigned long long)cnt && !zero) {
+                const double t = neg ? (N == 0.0 ? 0.0 : p - N) : N;
+                frac_add(num, den, t, D, p, pinv);
+            }
+            successor<M>(col, n);
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            const double n2 = shfl_xor_d(num, off), d2 = shfl_xor_d(den, off);
+            frac_add(num, den, n2, d2, p, pinv);
+        }
+        if (lane == 0) {
+            const double r = mulmod(num, invmod(den, p, pinv), p, pinv);
+            atomicAdd(&J.residues[(size_t)b * RADIC_MAX_PRIMES + pi], (unsigned long long)r);
+        }
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
+    __shared__ IntWaveLds<M> lds[kBatchWaves];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    IntWaveLds<M>& L = lds[wave];
+    constexpr int cls = RADIC_MAX_M + M - 1;   // class_of(1, M)
+    const unsigned long long total = J.header->chunks[cls];
+    const unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
+    int staged = -1;
+    for (;;) {
+        const unsigned long long g = take_chunk(&J.header->queue[cls], lane);
+        if (g >= total) break;
+        const int b = find_matrix(prefix, J.batch, g);
+        const unsigned long long c = g - prefix[b];
+        const radic_matrix_desc d = J.desc[b];
+        const BatchMeta mt = J.meta[b];
+        const bool restage = b != staged;
+        staged = b;
+        int_chunk<M>(J, d, mt, c, b, L, lane, restage);
+    }
+}
+
+// ---------------------------------------------------------------- finalize (one wave per matrix)
+__global__ __launch_bounds__(256) void k_batch_finalize(BatchJob J) {
+    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    if (wave >= J.batch) return;
+    const int b = wave;
+    const BatchMeta mt = J.meta[b];
+    radic_batch_result r{};
+    r.status = mt.status;
+    r.n_subsets = mt.kind >= 0 ? mt.total : 0;
+    if (mt.kind == 0) {
+        double hi = 0.0, lo = 0.0, ab = 0.0;
+        unsigned long long nfb = 0;
+        for (unsigned long long c = lane; c < mt.nchunks; c += kWave) {
+            const Partial p = J.partials[(size_t)b * kBatchChunksPerMatrix + c];
+            dd_add(hi, lo, p.hi, p.lo);
+            ab += p.abs;
+            nfb += p.nfb;
+        }
+        wave_reduce_partial(hi, lo, ab, nfb);
+        r.hi = ldexp(hi, mt.scale_exp);
+        r.lo = ldexp(lo, mt.scale_exp);
+        r.abs_sum = ldexp(ab, mt.scale_exp);
+        r.value = r.hi + r.lo;
+        r.n_fallback = nfb;
+    } else if (mt.kind == 1 && lane == 0) {
+        unsigned long long res[RADIC_MAX_PRIMES], pr[RADIC_MAX_PRIMES];
+        for (int i = 0; i < mt.n_primes; ++i) {
+            pr[i] = (unsigned long long)g_prime[i];
+            res[i] = J.residues[(size_t)b * RADIC_MAX_PRIMES + i] % pr[i];
+        }
+        unsigned mag[RADIC_MAX_PRIMES + 1];
+        int sign = 0, len = 0;
+        crt_to_limbs(res, pr, mt.n_primes, sign, len, mag);
+        r.n_primes = mt.n_primes;
+        r.sign = sign;
+        if (len > RADIC_MAX_PRIMES) {
+            r.status = RADIC_EOVERFLOW;
+        } else {
+            r.mag_len = len;
+            double v = 0.0;
+            for (int l = len - 1; l >= 0; --l) {
+                r.mag[l] = mag[l];
+                v = v * 4294967296.0 + (double)mag[l];
+            }
+            r.value = sign < 0 ? -v : v;
+            r.hi = r.value;
+        }
+    } else if (mt.kind == 0 || mt.kind == 1) {
+        return;
+    } else if (mt.status == RADIC_ENONFINITE) {
+        r.value = __builtin_nan("");
+    }
+    if (lane == 0) J.out[b] = r;
+}
+
+// ---------------------------------------------------------------- host side
+hipError_t upload_binomials_batched(const unsigned long long* t) { return upload_binomial_table(t); }
+hipError_t upload_primes_batched(const unsigned* primes, int count) { return upload_prime_table(primes, count); }
+size_t batched_workspace_bytes(int batch) { return batch_ws_bytes(batch); }
+
+// Persistent grid: as many workgroups as fit on the device at once.
+static int persistent_grid(const void* kernel, int block) {
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 1;
+    return cus * per;
+}
+
+template <bool F32, int M>
+static hipError_t launch_float_class(const BatchJob& J, hipStream_t s) {
+    static int grid = 0;
+    const int block = kBatchWaves * kWave;
+    if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_float<F32, M>), block);
+    hipLaunchKernelGGL((k_batch_float<F32, M>), dim3(grid), dim3(block), 0, s, J);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_int_class(const BatchJob& J, hipStream_t s) {
+    static int grid = 0;
+    const int block = kBatchWaves * kWave;
+    if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int<M>), block);
+    hipLaunchKernelGGL(k_batch_int<M>, dim3(grid), dim3(block), 0, s, J);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t launch_classes(const BatchJob& J, int prec, hipStream_t s) {
+    hipError_t e = prec == RADIC_FP32_BULK ? launch_float_class<true, M>(J, s) : launch_float_class<false, M>(J, s);
+    if (e == hipSuccess) e = launch_int_class<M>(J, s);
+    if (e != hipSuccess) return e;
+    if constexpr (M < RADIC_MAX_M) return launch_classes<M + 1>(J, prec, s);
+    return hipSuccess;
+}
+
+hipError_t launch_batched(const radic_matrix_desc* desc, int batch, const double* f64, const int* i32, int prec,
+                          double tau, int spl_float, int spl_int, int prime_count, radic_batch_result* out,
+                          void* ws, hipStream_t s) {
+    unsigned char* w = static_cast<unsigned char*>(ws);
+    BatchJob J{};
+    J.desc = desc;
+    J.batch = batch;
+    J.f64 = f64;
+    J.i32 = i32;
+    J.prec = prec;
+    J.tau = tau;
+    J.spl_float = spl_float;
+    J.spl_int = spl_int;
+    J.prime_count = prime_count;
+    J.out = out;
+    J.header = reinterpret_cast<BatchHeader*>(w);
+    J.meta = reinterpret_cast<BatchMeta*>(w + off_meta());
+    J.prefix = reinterpret_cast<unsigned long long*>(w + off_prefix(batch));
+    J.partials = reinterpret_cast<Partial*>(w + off_partials(batch));
+    J.residues = reinterpret_cast<unsigned long long*>(w + off_residues(batch));
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_batch_setup, dim3((batch + 255) / 256), dim3(256), 0, s, J);
+    hipLaunchKernelGGL(k_batch_scan, dim3(kClasses), dim3(1024), 0, s, J);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_classes<1>(J, prec, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batch_finalize, dim3((batch * kWave + 255) / 256), dim3(256), 0, s, J);
+    return hipGetLastError();
+}
+
+}  // namespace radic

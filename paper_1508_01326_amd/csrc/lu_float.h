@@ -1,0 +1,193 @@
+// LU with partial pivoting of register-resident minors, shared by the
+// single-matrix and batched floating-point kernels.
+#pragma once
+
+#include "enumerate.h"
+
+namespace radic {
+
+// ---------------------------------------------------------------- LDS layout
+// Columns are stored contiguously with a stride (in 16-byte groups) chosen odd so
+// that lanes reading different columns start on different bank groups.
+template <int M> struct Layout {
+    static constexpr int g64 = (((M + 1) / 2) % 2 == 0) ? (M + 1) / 2 + 1 : (M + 1) / 2;
+    static constexpr int st64 = 2 * g64;                  // doubles per column
+    static constexpr int g32 = (((M + 4) / 4) % 2 == 0) ? (M + 4) / 4 + 1 : (M + 4) / 4;
+    static constexpr int st32 = 4 * g32;                  // floats per column (+1 slot: column scale)
+};
+
+// Per-wave fallback region: queue of 16-byte entries + M x M double scratch.
+template <int M> __host__ __device__ constexpr int fallback_wave_bytes() {
+    return kFallbackCap * 16 + align16(M * M * 8);
+}
+
+// ---------------------------------------------------------------- LU building blocks
+template <int M, typename T>
+__device__ __forceinline__ void gather(T (&a)[M][M], const T* base, int stride, const int (&col)[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const T* src = base + col[j] * stride;
+        if constexpr (sizeof(T) == 8) {
+#pragma unroll
+            for (int i = 0; i + 1 < M; i += 2) {
+                double2 v = *reinterpret_cast<const double2*>(src + i);
+                a[i][j] = v.x;
+                a[i + 1][j] = v.y;
+            }
+            if (M & 1) a[M - 1][j] = src[M - 1];
+        } else {
+#pragma unroll
+            for (int i = 0; i + 3 < M; i += 4) {
+                float4 v = *reinterpret_cast<const float4*>(src + i);
+                a[i][j] = v.x;
+                a[i + 1][j] = v.y;
+                a[i + 2][j] = v.z;
+                a[i + 3][j] = v.w;
+            }
+#pragma unroll
+            for (int i = (M / 4) * 4; i < M; ++i) a[i][j] = src[i];
+        }
+    }
+}
+
+// Bring each lane's pivot row p into row K with selects.  Only candidate rows
+// that some lane of the wave chose are visited (a wave-uniform test), so a step
+// on which the whole wave keeps row K costs one ballot per candidate.  When every
+// lane of the wave chose the same row i, the exchange (K, i) is recorded in the
+// wave's row order `perm` (4 bits per position) and its parity flipped, so that
+// the next minors are gathered with that exchange already applied.
+template <int M, int K, typename T>
+__device__ __forceinline__ void exchange_rows(T (&a)[M][M], int p, unsigned long long& perm, int& perm_odd) {
+#pragma unroll
+    for (int i = K + 1; i < M; ++i) {
+        const bool c = (p == i);
+        const unsigned long long mask = __ballot(c);
+        if (mask) {
+            if (mask == ~0ull) {
+                const unsigned long long x = ((perm >> (4 * K)) ^ (perm >> (4 * i))) & 15ull;
+                perm ^= (x << (4 * K)) | (x << (4 * i));
+                perm_odd ^= 1;
+            }
+#pragma unroll
+            for (int j = K; j < M; ++j) {
+                const T x = a[K][j], y = a[i][j];
+                a[K][j] = c ? y : x;
+                a[i][j] = c ? x : y;
+            }
+        }
+    }
+}
+
+// LU with partial pivoting of the register-resident minor, one step per
+// template level K so that every register index is a compile-time constant.
+// Accumulates the pivots into det, raises `zero` for an exactly zero pivot
+// column, flips `neg` once per row exchange and, for FP32 (CHECK), raises `flag`
+// when a pivot falls below tau * s_k.
+template <int M, int K, typename T, bool CHECK>
+__device__ __forceinline__ void lu_steps(T (&a)[M][M], T& det, bool& zero, bool& neg, float& ratio,
+                                         const T (&s)[M], unsigned long long& perm, int& perm_odd) {
+    if constexpr (K < M - 1) {
+        unsigned best = pivot_key(a[K][K], K);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(a[i][K], i));
+        const int p = pivot_row(best);
+        neg ^= (p != K);
+        exchange_rows<M, K, T>(a, p, perm, perm_odd);
+        const T piv = a[K][K];
+        zero |= (piv == T(0));
+        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)s[K]);
+        det *= piv;
+        const T r = recip(piv);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) {
+            const T l = a[i][K] * r;
+#pragma unroll
+            for (int j = K + 1; j < M; ++j) a[i][j] = fma_t(-l, a[K][j], a[i][j]);
+        }
+        lu_steps<M, K + 1, T, CHECK>(a, det, zero, neg, ratio, s, perm, perm_odd);
+    }
+}
+
+// Determinant of the minor (0 for an exactly zero pivot column).  For FP32
+// (CHECK) `flag` is raised when prod_k min(1, |u_kk| / s_k) < tau, s_k the largest
+// magnitude in the minor's k-th column of the row-scaled matrix (s holds 1/s_k):
+// the minor is then relatively ill-conditioned, float elimination may have lost
+// too many digits, and the minor is refactored in double.
+template <int M, typename T, bool CHECK>
+__device__ __forceinline__ T lu_det(T (&a)[M][M], bool& neg, bool& flag, const T (&s)[M], T tau,
+                                    unsigned long long& perm, int& perm_odd) {
+    T det = T(1);
+    bool zero = false;
+    float ratio = 1.0f;
+    lu_steps<M, 0, T, CHECK>(a, det, zero, neg, ratio, s, perm, perm_odd);
+    const T last = a[M - 1][M - 1];
+    if (CHECK) {
+        ratio *= __saturatef(__builtin_fabsf((float)last) * (float)s[M - 1]);
+        flag |= !(ratio >= (float)tau);
+    }
+    det *= last;
+    return zero ? T(0) : det;
+}
+
+// ---------------------------------------------------------------- FP64 refactorisation (wave-cooperative)
+// One minor at a time, factored by the whole wave in LDS: exact first-maximum
+// partial pivoting and true division, as in the textbook algorithm.
+template <int M>
+__device__ double coop_det_f64(const double* cd, const int (&c)[M], double* W, int lane) {
+    constexpr int ST64 = Layout<M>::st64;
+    for (int t = lane; t < M * M; t += kWave) {
+        int i = t / M, j = t - i * M;
+        W[t] = cd[c[j] * ST64 + i];
+    }
+    wave_lds_sync();
+    double det = 1.0;
+    bool neg = false, zero = false;
+    for (int k = 0; k < M; ++k) {
+        double v = (lane >= k && lane < M) ? fabs(W[lane * M + k]) : -1.0;
+        if (v != v) v = __builtin_inf();   // a NaN entry is taken as the largest
+        int idx = lane;
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            double v2 = shfl_xor_d(v, off);
+            int i2 = __shfl_xor(idx, off, kWave);
+            if (v2 > v || (v2 == v && i2 < idx)) { v = v2; idx = i2; }
+        }
+        if (v == 0.0) { zero = true; break; }
+        const int p = (idx >= k && idx < M) ? idx : k;
+        if (p != k) {
+            neg = !neg;
+            if (lane >= k && lane < M) {
+                double x = W[k * M + lane];
+                W[k * M + lane] = W[p * M + lane];
+                W[p * M + lane] = x;
+            }
+        }
+        wave_lds_sync();
+        const double piv = W[k * M + k];
+        det *= piv;
+        const int w = M - 1 - k;
+        for (int t = lane; t < w * w; t += kWave) {
+            int i = k + 1 + t / w, j = k + 1 + t % w;
+            double l = W[i * M + k] / piv;
+            W[i * M + j] -= l * W[k * M + j];
+        }
+        wave_lds_sync();
+    }
+    return zero ? 0.0 : (neg ? -det : det);
+}
+
+template <int M>
+__device__ __forceinline__ void pack_cols(const int (&col)[M], unsigned (&w)[3]) {
+    w[0] = w[1] = w[2] = 0u;
+#pragma unroll
+    for (int j = 0; j < M; ++j) w[j / 4] |= (unsigned)col[j] << (8 * (j % 4));
+}
+
+template <int M>
+__device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
+#pragma unroll
+    for (int j = 0; j < M; ++j) col[j] = (w[j / 4] >> (8 * (j % 4))) & 0xFF;
+}
+
+// Refactor every queued minor in double; lane 0 accumulates the terms.
+}  // namespace radic

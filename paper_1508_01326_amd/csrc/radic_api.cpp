@@ -9,6 +9,7 @@
 #include <initializer_list>
 #include <map>
 #include <mutex>
+#include <new>
 #include <tuple>
 #include <vector>
 
@@ -28,6 +29,12 @@ hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned l
                            int grid_x, int n_primes, int block, void* ws, hipStream_t s);
 hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s);
 size_t int_workspace_bytes();
+hipError_t upload_binomials_batched(const unsigned long long* t);
+hipError_t upload_primes_batched(const unsigned* primes, int count);
+size_t batched_workspace_bytes(int batch);
+hipError_t launch_batched(const radic_matrix_desc* desc, int batch, const double* f64, const int* i32, int prec,
+                          double tau, int spl_float, int spl_int, int prime_count, radic_batch_result* out,
+                          void* ws, hipStream_t s);
 size_t int_result_offset();
 size_t int_result_size();
 int int_lds(int m, int n);
@@ -120,6 +127,7 @@ static int ensure_device() {
     std::lock_guard<std::mutex> lk(g_mu);
     if (g_dev_prime_version[dev] != g_prime_version) {
         hipError_t pe = upload_primes(g_primes.data(), (int)g_primes.size());
+        if (pe == hipSuccess) pe = upload_primes_batched(g_primes.data(), (int)g_primes.size());
         if (pe != hipSuccess) return device_error("upload of the prime set", pe);
         g_dev_prime_version[dev] = g_prime_version;
     }
@@ -133,6 +141,7 @@ static int ensure_device() {
         }
     hipError_t ue = upload_binomials_float(t.data());
     if (ue == hipSuccess) ue = upload_binomials_int(t.data());
+    if (ue == hipSuccess) ue = upload_binomials_batched(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
     return RADIC_OK;
@@ -148,10 +157,12 @@ static int g_force_spl = 0, g_force_block = 0;
 static double g_tau = 1.0 / 1024.0;
 
 static Shape default_shape(int kind, int prec, int m, int n) {
-    (void)kind;
-    (void)prec;
     (void)n;
     Shape s{8, 256};
+    if (kind == RADIC_WS_BATCHED) {
+        s.spl = prec == 2 ? 4 : 8;   // prec 2: the exact kernel
+        return s;
+    }
     if (m <= 3) s.spl = 32;
     return s;
 }
@@ -323,6 +334,9 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch) {
         case RADIC_WS_INT:
             if (m < 1 || n < 1) return 0;
             return int_workspace_bytes();
+        case RADIC_WS_BATCHED:
+            if (batch < 1) return 0;
+            return batched_workspace_bytes(batch);
         default:
             (void)batch;
             return 0;
@@ -427,17 +441,100 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     return RADIC_OK;
 }
 
-int radic_det_batched(const radic_matrix_desc*, int, const double*, const int32_t*, int, radic_batch_result*,
-                      void*, size_t, hipStream_t) {
-    return RADIC_ENOTSUP;
+int radic_det_batched(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32, int prec,
+                      radic_batch_result* dOut, void* dWork, size_t work_bytes, hipStream_t stream) {
+    if (!dDesc || !dOut || batch < 0) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (batch == 0) return RADIC_OK;
+    if (batch > (1 << 24)) return RADIC_ENOTSUP;
+    int rc = check_workspace(dWork, work_bytes, batched_workspace_bytes(batch));
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    const Shape sf = pick_shape(RADIC_WS_BATCHED, prec, 0, 0);
+    const Shape si = pick_shape(RADIC_WS_BATCHED, 2, 0, 0);
+    double tau;
+    int prime_count;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        tau = g_tau;
+        prime_count = (int)g_primes.size();
+    }
+    hipError_t e;
+    {
+        ProfScope ps(stream);
+        e = launch_batched(dDesc, batch, dF64, reinterpret_cast<const int*>(dI32), prec, tau, sf.spl, si.spl,
+                           prime_count, dOut, dWork, stream);
+    }
+    return e == hipSuccess ? RADIC_OK : device_error("launch of the batched kernels", e);
 }
 
-int radic_batched_graph_create(const radic_matrix_desc*, int, const double*, const int32_t*, int,
-                               radic_batch_result*, void*, size_t, void**) {
-    return RADIC_ENOTSUP;
+struct GraphHandle {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int radic_batched_graph_create(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32,
+                               int prec, radic_batch_result* dOut, void* dWork, size_t work_bytes, void** hGraph) {
+    if (!hGraph) return RADIC_EINVAL;
+    *hGraph = nullptr;
+    if (!dDesc || !dOut || batch < 1) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    int rc = check_workspace(dWork, work_bytes, batched_workspace_bytes(batch));
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;   // table uploads happen outside the capture
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return device_error("hipStreamCreateWithFlags", e);
+    GraphHandle* h = new (std::nothrow) GraphHandle();
+    if (!h) {
+        (void)hipStreamDestroy(cs);
+        return RADIC_ENOMEM;
+    }
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int lrc = radic_det_batched(dDesc, batch, dF64, dI32, prec, dOut, dWork, work_bytes, cs);
+        hipError_t ee = hipStreamEndCapture(cs, &h->graph);
+        if (lrc != RADIC_OK) rc = lrc;
+        else if (ee != hipSuccess) rc = device_error("hipStreamEndCapture", ee);
+        else {
+            ee = hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0);
+            if (ee != hipSuccess) rc = device_error("hipGraphInstantiate", ee);
+        }
+    } else {
+        rc = device_error("hipStreamBeginCapture", e);
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc != RADIC_OK) {
+        if (h->exec) (void)hipGraphExecDestroy(h->exec);
+        if (h->graph) (void)hipGraphDestroy(h->graph);
+        delete h;
+        return rc;
+    }
+    *hGraph = h;
+    return RADIC_OK;
 }
-int radic_graph_launch(void*, hipStream_t) { return RADIC_ENOTSUP; }
-int radic_graph_destroy(void*) { return RADIC_ENOTSUP; }
+
+int radic_graph_launch(void* hGraph, hipStream_t stream) {
+    if (!hGraph) return RADIC_EINVAL;
+    GraphHandle* h = static_cast<GraphHandle*>(hGraph);
+    hipError_t e;
+    {
+        ProfScope ps(stream);
+        e = hipGraphLaunch(h->exec, stream);
+    }
+    return e == hipSuccess ? RADIC_OK : device_error("hipGraphLaunch", e);
+}
+
+int radic_graph_destroy(void* hGraph) {
+    if (!hGraph) return RADIC_EINVAL;
+    GraphHandle* h = static_cast<GraphHandle*>(hGraph);
+    hipError_t e1 = h->exec ? hipGraphExecDestroy(h->exec) : hipSuccess;
+    hipError_t e2 = h->graph ? hipGraphDestroy(h->graph) : hipSuccess;
+    delete h;
+    if (e1 != hipSuccess) return device_error("hipGraphExecDestroy", e1);
+    if (e2 != hipSuccess) return device_error("hipGraphDestroy", e2);
+    return RADIC_OK;
+}
 
 int radic_autotune(int, int, int, int, int*, hipStream_t) { return RADIC_ENOTSUP; }
 int radic_tune_save(const char*) { return RADIC_ENOTSUP; }

@@ -1,0 +1,147 @@
+"""GPU parity of the batched persistent path (and its HIP-graph launch)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.parity import TOL, normaliser
+
+pytestmark = pytest.mark.gpu
+
+radic = pytest.importorskip("paper_1508_01326_amd")
+
+
+@pytest.fixture(autouse=True)
+def _defaults():
+    radic.set_launch(0, 0)
+    radic.set_fallback_tau(1.0 / 1024)
+    radic.set_prime_set([])
+    yield
+
+
+def mixed_batch(count, seed, m_max=8, n_max=14):
+    rng = np.random.default_rng(seed)
+    mats = []
+    for b in range(count):
+        m = int(rng.integers(1, m_max + 1))
+        n = int(rng.integers(m, n_max + 1))
+        if b % 2 == 0:
+            mats.append(rng.standard_normal((m, n)))
+        else:
+            mats.append(rng.integers(-40, 41, size=(m, n)).astype(np.int32))
+    return mats
+
+
+def check(mats, res, precision, idx=None):
+    for b in (range(len(mats)) if idx is None else idx):
+        A, r = mats[b], res[b]
+        m, n = A.shape
+        assert r["status"] == 0, (b, r)
+        assert r["n_subsets"] == (math.comb(n, m) if m <= n else 0)
+        if A.dtype == np.int32:
+            assert r["exact"] == oracle.radic_int(A), b
+        else:
+            ref = oracle.radic_f64(A)
+            S = normaliser(ref["abs_sum"], A)
+            assert abs(r["value"] - ref["value"]) <= TOL[precision] * S, (b, r["value"], ref["value"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_mixed_batch(precision):
+    mats = mixed_batch(96, seed=1)
+    print(f"[case] batched mixed 96 {precision}", flush=True)
+    B = radic.Batch(mats)
+    res = radic.radic_det_batched(B, precision)
+    check(mats, res, precision)
+
+
+def test_every_row_count():
+    # one float and one int matrix for every m = 1..12 (each has its own class kernel)
+    rng = np.random.default_rng(2)
+    mats = []
+    for m in range(1, 13):
+        n = m + int(rng.integers(0, 4))
+        mats.append(rng.standard_normal((m, n)))
+        mats.append(rng.integers(-9, 10, size=(m, n)).astype(np.int32))
+    print("[case] batched m=1..12", flush=True)
+    res = radic.radic_det_batched(radic.Batch(mats), "fp64")
+    check(mats, res, "fp64")
+
+
+def test_bad_descriptors_reported_per_matrix():
+    good = np.random.default_rng(3).standard_normal((3, 7))
+    mats = [good, np.ones((5, 4)), np.zeros((2, 70)), good.copy()]
+    mats[3][1, 2] = np.nan
+    B = radic.Batch(mats)
+    # corrupt descriptor 0's lda below n
+    d = B.desc_host.copy()
+    bad = d.copy()
+    bad[0]["lda"] = 2
+    import torch
+    B.desc = torch.from_numpy(bad.view(np.uint8).copy()).to("cuda")
+    print("[case] batched bad descriptors", flush=True)
+    res = radic.radic_det_batched(B, "fp64")
+    assert res[0]["status"] == radic.RADIC_EINVAL
+    assert res[1]["status"] == 0 and res[1]["value"] == 0.0          # m > n
+    assert res[2]["status"] == radic.RADIC_ENOTSUP                   # n beyond the batched limit
+    assert res[3]["status"] == radic.RADIC_ENONFINITE and math.isnan(res[3]["value"])
+
+
+def test_bitwise_reproducible_batched():
+    mats = mixed_batch(40, seed=4)
+    B = radic.Batch(mats)
+    r1 = radic.radic_det_batched(B, "fp32_bulk")
+    r2 = radic.radic_det_batched(B, "fp32_bulk")
+    for a, b in zip(r1, r2):
+        assert a["hi"] == b["hi"] and a["lo"] == b["lo"] and a["exact"] == b["exact"]
+
+
+def test_graph_replays():
+    import torch
+    mats = mixed_batch(50, seed=5)
+    B = radic.Batch(mats)
+    direct = radic.radic_det_batched(B, "fp64")
+    G = radic.BatchGraph(B, "fp64")
+    try:
+        for rep in range(3):
+            B.out.zero_()
+            torch.cuda.synchronize()
+            print(f"[case] graph replay {rep}", flush=True)
+            G.launch()
+            torch.cuda.synchronize()
+            res = B.results()
+            for a, b in zip(direct, res):
+                assert a["hi"] == b["hi"] and a["lo"] == b["lo"] and a["exact"] == b["exact"]
+            # eager work between replays
+            _ = (torch.ones(1000, device="cuda") * 2).sum().item()
+        # new contents, same shapes: the replay reflects them
+        mats2 = [(-A if A.dtype == np.float64 else (A * 2).astype(np.int32)) for A in mats]
+        B2 = radic.Batch(mats2)
+        B.f64.copy_(B2.f64)
+        B.i32.copy_(B2.i32)
+        torch.cuda.synchronize()
+        G.launch()
+        torch.cuda.synchronize()
+        check(mats2, B.results(), "fp64")
+    finally:
+        G.destroy()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_workload5_sampled(precision):
+    batch = workloads.batch_matrices()
+    mats = [A for _, A in batch]
+    print(f"[case] workload5 4096 {precision}", flush=True)
+    res = radic.radic_det_batched(radic.Batch(mats), precision)
+    assert sum(r["n_subsets"] for r in res) == 342865835
+    assert all(r["status"] == 0 for r in res)
+    rng = np.random.default_rng(55)
+    small = [b for b, A in enumerate(mats) if math.comb(A.shape[1], A.shape[0]) <= 20000]
+    idx = list(rng.choice(small, size=48, replace=False))
+    # plus the largest matrix of each type
+    for kind in ("f64", "i32"):
+        cands = [b for b, (k, A) in enumerate(batch) if k == kind]
+        idx.append(max(cands, key=lambda b: math.comb(mats[b].shape[1], mats[b].shape[0])))
+    check(mats, res, precision, idx)
