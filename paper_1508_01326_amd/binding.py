@@ -244,6 +244,24 @@ def radic_det_int_exact(A, work=None, stream=None, cap=RADIC_MAX_PRIMES + 2):
     return -v if sign.value < 0 else v
 
 
+def autotune(kind, m=0, n=0, precision="fp64", stream=None):
+    """Time launch shapes for (kind, m, n, precision) and keep the fastest;
+    returns (subsets_per_lane, block).  For RADIC_WS_BATCHED, precision "exact"
+    tunes the exact persistent kernels."""
+    prec = {"fp64": 0, "fp32_bulk": 1, "exact": 2}[precision] if isinstance(precision, str) else int(precision)
+    best = (ctypes.c_int * 2)()
+    _check(lib().radic_autotune(int(kind), int(m), int(n), prec, best, _stream_handle(stream)), "radic_autotune")
+    return best[0], best[1]
+
+
+def tune_save(path):
+    _check(lib().radic_tune_save(str(path).encode()), "radic_tune_save")
+
+
+def tune_load(path):
+    _check(lib().radic_tune_load(str(path).encode()), "radic_tune_load")
+
+
 def set_launch(subsets_per_lane=0, block_size=0):
     _check(lib().radic_set_launch(int(subsets_per_lane), int(block_size)), "radic_set_launch")
 

@@ -214,13 +214,12 @@ __device__ __forceinline__ int find_matrix(const unsigned long long* prefix, int
 
 // ---------------------------------------------------------------- float chunks
 // Per-wave LDS of a float class: the double copy of the staged matrix, and for
-// FP32_BULK the float copy (with the column-scale slot), the fallback queue and
-// the scratch of the wave-cooperative double refactorisation.
+// FP32_BULK the float copy (with the column-scale slot), the queue of minors to
+// refactor in double and the row exponents.
 template <int M, bool F32> struct FloatWaveLds {
     double cd[kBatchMaxN * Layout<M>::st64];
     float cf[F32 ? kBatchMaxN * Layout<M>::st32 : 1];
     unsigned queue[F32 ? 4 * kFallbackCap : 1];
-    double W[F32 ? M * M : 1];
     int rowexp[M];
 };
 
@@ -251,25 +250,6 @@ __device__ void stage_float(const BatchJob& J, const radic_matrix_desc& d, Float
 #pragma unroll
             for (int i = 0; i < M; ++i) s = fmaxf(s, fabsf(L.cf[j * ST32 + i]));
             L.cf[j * ST32 + M] = s > 0.f ? 1.0f / s : 0.f;
-        }
-        wave_lds_sync();
-    }
-}
-
-template <int M>
-__device__ void flush_batch_fallback(const double* cd, unsigned* queue, int count, double* W, int lane, double& hi,
-                                     double& lo, double& ab) {
-    for (int e = 0; e < count; ++e) {
-        int c[M];
-        unpack_cols<M>(queue + 4 * e, c);
-        const double d = coop_det_f64<M>(cd, c, W, lane);
-        const double term = radic_sign_odd<M>(c) ? -d : d;
-        if (lane == 0) {
-            double s, err;
-            two_sum(hi, term, s, err);
-            hi = s;
-            lo += err;
-            ab += fabs(d);
         }
         wave_lds_sync();
     }
@@ -339,7 +319,7 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
                 qcount += __popcll(fm);
                 if (qcount > kFallbackCap - kWave) {
                     wave_lds_sync();
-                    flush_batch_fallback<M>(L.cd, L.queue, qcount, L.W, lane, hi, lo, ab);
+                    refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab, [](int, double) {});
                     qcount = 0;
                 }
             }
@@ -348,7 +328,7 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
     }
     if (F32 && qcount > 0) {
         wave_lds_sync();
-        flush_batch_fallback<M>(L.cd, L.queue, qcount, L.W, lane, hi, lo, ab);
+        refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab, [](int, double) {});
     }
     wave_reduce_partial(hi, lo, ab, nfb);
     out = Partial{hi, lo, ab, nfb};

@@ -16,7 +16,8 @@ template <int M> struct Layout {
     static constexpr int st32 = 4 * g32;                  // floats per column (+1 slot: column scale)
 };
 
-// Per-wave fallback region: queue of 16-byte entries + M x M double scratch.
+// Per-wave fallback region: queue of 16-byte entries (packed columns, rank
+// offset) followed by the M x M double scratch of the wave-cooperative LU.
 template <int M> __host__ __device__ constexpr int fallback_wave_bytes() {
     return kFallbackCap * 16 + align16(M * M * 8);
 }
@@ -189,5 +190,37 @@ __device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
     for (int j = 0; j < M; ++j) col[j] = (w[j / 4] >> (8 * (j % 4))) & 0xFF;
 }
 
-// Refactor every queued minor in double; lane 0 accumulates the terms.
+// Refactor queued minors in double, one minor per lane (rows in natural order,
+// from the row-scaled double copy cd); lane l takes entries l, l + 64, ...
+// Each lane adds its terms to its own double-double sum.  `on_term(entry, term)`
+// is called for every valid entry (export of individual terms).
+template <int M, typename OnTerm>
+__device__ void refactor_queue_f64(const double* cd, const unsigned* queue, int count, int lane, double& hi,
+                                   double& lo, double& ab, OnTerm on_term) {
+    constexpr int ST64 = Layout<M>::st64;
+    for (int base = 0; base < count; base += kWave) {
+        const int e = base + lane;
+        const bool valid = e < count;
+        int c[M];
+        unpack_cols<M>(queue + 4 * (valid ? e : base), c);
+        double a[M][M];
+        gather<M, double>(a, cd, ST64, c);
+        bool neg = radic_sign_odd<M>(c);
+        bool flag = false;
+        unsigned long long perm = 0;
+        int perm_odd = 0;
+        const double unused[M] = {};
+        const double d = lu_det<M, double, false>(a, neg, flag, unused, 0.0, perm, perm_odd);
+        if (valid) {
+            const double term = neg ? -d : d;
+            double s, err;
+            two_sum(hi, term, s, err);
+            hi = s;
+            lo += err;
+            ab += fabs(d);
+            on_term(e, term);
+        }
+    }
+}
+
 }  // namespace radic

@@ -2,7 +2,9 @@
 // selection and dispatch to the HIP kernels.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <functional>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -18,8 +20,9 @@
 namespace radic {
 
 hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, int grid, int block, hipStream_t s);
-hipError_t launch_finalize_float(const Partial* parts, int G, const DetHeader* h, radic_f64_result* out,
-                                 unsigned long long count, int use_scale, hipStream_t s);
+hipError_t launch_finalize_float(const Partial* parts, const Partial* fb_parts, int G, const DetHeader* h,
+                                 radic_f64_result* out, unsigned long long count, int use_scale, hipStream_t s);
+hipError_t launch_refactor(int m, const FloatJob& J, int grid, int block, hipStream_t s);
 hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s);
 hipError_t upload_binomials_float(const unsigned long long* host_table);
 hipError_t upload_binomials_int(const unsigned long long* host_table);
@@ -219,7 +222,13 @@ static int check_workspace(void* ws, size_t bytes, size_t need) {
     return RADIC_OK;
 }
 
-static size_t det_workspace_bytes() { return kHeaderBytes + sizeof(Partial) * (size_t)kMaxGrid; }
+// Single-matrix workspace: header | partials[kMaxGrid] | refactor partials[kMaxGrid] |
+// per-wave segment counts [kMaxGrid*4] | per-wave segments [kMaxGrid*4][kDeferCap] (16 B entries)
+static size_t ws_partials() { return kHeaderBytes; }
+static size_t ws_fb_partials() { return ws_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
+static size_t ws_fb_count() { return ws_fb_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
+static size_t ws_fb_entries() { return ws_fb_count() + sizeof(unsigned) * (size_t)kMaxGrid * 4; }
+static size_t det_workspace_bytes() { return ws_fb_entries() + 16 * (size_t)kMaxGrid * 4 * kDeferCap; }
 
 static int float_common_checks(const double* dA, int m, int n, long long lda, int prec) {
     if (!dA || m < 1 || n < 1 || lda < n) return RADIC_EINVAL;
@@ -290,21 +299,89 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         J.tau = g_tau;
     }
     J.header = reinterpret_cast<DetHeader*>(ws);
-    J.partials = reinterpret_cast<Partial*>(ws + kHeaderBytes);
+    J.partials = reinterpret_cast<Partial*>(ws + ws_partials());
+    J.fb_partials = reinterpret_cast<Partial*>(ws + ws_fb_partials());
+    J.fb_count = reinterpret_cast<unsigned*>(ws + ws_fb_count());
+    J.fb_entries = reinterpret_cast<unsigned*>(ws + ws_fb_entries());
     const int grid = grid_for(J.chunks, sh.block);
+    const bool defer = prec == RADIC_FP32_BULK;
     hipError_t e;
     {
         ProfScope ps(stream);
         e = launch_float(m, prec, false, J, grid, sh.block, stream);
     }
     if (e != hipSuccess) return device_error("launch of the enumeration kernel", e);
-    e = launch_finalize_float(J.partials, grid, J.header, dOut, count, prec == RADIC_FP32_BULK, stream);
+    if (defer) {
+        e = launch_refactor(m, J, grid, sh.block, stream);
+        if (e != hipSuccess) return device_error("launch of the refactorisation kernel", e);
+    }
+    e = launch_finalize_float(J.partials, defer ? J.fb_partials : nullptr, grid, J.header, dOut, count, defer,
+                              stream);
     return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
 }
 
 }  // namespace radic
 
 using namespace radic;
+
+// ---------------------------------------------------------------- autotuning
+namespace {
+
+// Deterministic synthetic inputs for tuning (xorshift64*, Box-Muller free: uniform in [-1, 1)).
+struct TuneRng {
+    unsigned long long s;
+    explicit TuneRng(unsigned long long seed) : s(seed ? seed : 0x9E3779B97F4A7C15ull) {}
+    unsigned long long next() {
+        s ^= s >> 12;
+        s ^= s << 25;
+        s ^= s >> 27;
+        return s * 0x2545F4914F6CDD1Dull;
+    }
+    double uniform() { return (double)(next() >> 11) * (2.0 / 9007199254740992.0) - 1.0; }
+};
+
+struct DeviceBuffers {
+    std::vector<void*> ptrs;
+    ~DeviceBuffers() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    void* alloc(size_t bytes) {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+};
+
+// Median of `reps` timed runs of fn() on `stream` (after one warm-up), in ms.
+template <typename F>
+static float time_runs(F fn, hipStream_t stream, int reps, int* rc_out) {
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        *rc_out = RADIC_EDEVICE;
+        return 0.f;
+    }
+    std::vector<float> t;
+    int rc = fn();
+    (void)hipStreamSynchronize(stream);
+    for (int r = 0; r < reps && rc == RADIC_OK; ++r) {
+        (void)hipEventRecord(a, stream);
+        rc = fn();
+        (void)hipEventRecord(b, stream);
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        t.push_back(ms);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *rc_out = rc;
+    if (t.empty()) return 0.f;
+    std::sort(t.begin(), t.end());
+    return t[t.size() / 2];
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -536,9 +613,154 @@ int radic_graph_destroy(void* hGraph) {
     return RADIC_OK;
 }
 
-int radic_autotune(int, int, int, int, int*, hipStream_t) { return RADIC_ENOTSUP; }
-int radic_tune_save(const char*) { return RADIC_ENOTSUP; }
-int radic_tune_load(const char*) { return RADIC_ENOTSUP; }
+
+int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t stream) {
+    if (kind != RADIC_WS_DET && kind != RADIC_WS_INT && kind != RADIC_WS_BATCHED) return RADIC_EINVAL;
+    if (kind == RADIC_WS_DET && prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (kind == RADIC_WS_BATCHED && prec != RADIC_FP64 && prec != RADIC_FP32_BULK && prec != 2) return RADIC_EINVAL;
+    if (kind != RADIC_WS_BATCHED && (m < 1 || n < m || m > RADIC_MAX_M || n > RADIC_MAX_N)) return RADIC_EINVAL;
+    int rc = ensure_device();
+    if (rc != RADIC_OK) return rc;
+    unsigned long long total = 0;
+    if (kind != RADIC_WS_BATCHED && (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit))
+        return RADIC_EOVERFLOW;
+    int saved_spl, saved_block;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        saved_spl = g_force_spl;
+        saved_block = g_force_block;
+    }
+    DeviceBuffers buf;
+    TuneRng rng(0x5eed0000ull + (unsigned long long)(kind * 1000003 + m * 1009 + n));
+    std::function<int()> run;
+    const int spls[] = {1, 2, 4, 8, 16, 32, 64};
+    std::vector<int> blocks = {64, 128, 256};
+    std::vector<double> hf;
+    std::vector<int> hi;
+    radic_matrix_desc* dDesc = nullptr;
+    int batch = 0;
+    if (kind == RADIC_WS_DET) {
+        hf.resize((size_t)m * n);
+        for (double& x : hf) x = rng.uniform();
+        double* dA = static_cast<double*>(buf.alloc(hf.size() * 8));
+        void* out = buf.alloc(sizeof(radic_f64_result));
+        void* ws = buf.alloc(det_workspace_bytes());
+        if (!dA || !out || !ws) return RADIC_ENOMEM;
+        if (hipMemcpy(dA, hf.data(), hf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return RADIC_EDEVICE;
+        run = [=]() { return radic_det(dA, m, n, n, prec, static_cast<radic_f64_result*>(out), ws,
+                                       det_workspace_bytes(), stream); };
+    } else if (kind == RADIC_WS_INT) {
+        hi.resize((size_t)m * n);
+        for (int& x : hi) x = (int)(rng.next() % 19) - 9;
+        int* dA = static_cast<int*>(buf.alloc(hi.size() * 4));
+        void* ws = buf.alloc(int_workspace_bytes());
+        if (!dA || !ws) return RADIC_ENOMEM;
+        if (hipMemcpy(dA, hi.data(), hi.size() * 4, hipMemcpyHostToDevice) != hipSuccess) return RADIC_EDEVICE;
+        run = [=]() {
+            uint32_t mag[RADIC_MAX_PRIMES + 1];
+            int len = 0, sg = 0;
+            return radic_det_int_exact(dA, m, n, n, mag, RADIC_MAX_PRIMES + 1, &len, &sg, ws, int_workspace_bytes(),
+                                       stream);
+        };
+    } else {
+        // a synthetic mixed batch of the shapes the persistent kernels serve (m in [2, 10], n in [m, 24])
+        batch = 512;
+        std::vector<radic_matrix_desc> desc((size_t)batch);
+        long long fo = 0, io = 0;
+        for (int b = 0; b < batch; ++b) {
+            const int mm = 2 + (int)(rng.next() % 9);
+            const int nn = mm + (int)(rng.next() % (25 - mm));
+            const int dt = prec == 2 ? 1 : (b % 2);
+            desc[(size_t)b] = radic_matrix_desc{mm, nn, dt, 0, dt ? io : fo, nn};
+            for (int e = 0; e < mm * nn; ++e) {
+                if (dt) hi.push_back((int)(rng.next() % 256));
+                else hf.push_back(rng.uniform());
+            }
+            (dt ? io : fo) += (long long)mm * nn;
+        }
+        dDesc = static_cast<radic_matrix_desc*>(buf.alloc(sizeof(radic_matrix_desc) * batch));
+        double* dF = static_cast<double*>(buf.alloc(std::max<size_t>(hf.size(), 1) * 8));
+        int* dI = static_cast<int*>(buf.alloc(std::max<size_t>(hi.size(), 1) * 4));
+        void* out = buf.alloc(sizeof(radic_batch_result) * batch);
+        const size_t wsb = batched_workspace_bytes(batch);
+        void* ws = buf.alloc(wsb);
+        if (!dDesc || !dF || !dI || !out || !ws) return RADIC_ENOMEM;
+        if (hipMemcpy(dDesc, desc.data(), sizeof(radic_matrix_desc) * batch, hipMemcpyHostToDevice) != hipSuccess ||
+            (!hf.empty() && hipMemcpy(dF, hf.data(), hf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) ||
+            (!hi.empty() && hipMemcpy(dI, hi.data(), hi.size() * 4, hipMemcpyHostToDevice) != hipSuccess))
+            return RADIC_EDEVICE;
+        const int p = prec == 2 ? RADIC_FP64 : prec;
+        run = [=]() { return radic_det_batched(dDesc, batch, dF, dI, p, static_cast<radic_batch_result*>(out), ws,
+                                               wsb, stream); };
+        blocks = {256};   // the persistent kernels have a fixed workgroup
+    }
+    float best_ms = 0.f;
+    Shape best{0, 0};
+    for (int spl : spls) {
+        for (int block : blocks) {
+            {
+                std::lock_guard<std::mutex> lk(g_mu);
+                g_force_spl = spl;
+                g_force_block = block;
+            }
+            int trc = RADIC_OK;
+            const float ms = time_runs(run, stream, 3, &trc);
+            if (trc != RADIC_OK) continue;
+            if (best.spl == 0 || ms < best_ms) {
+                best_ms = ms;
+                best = Shape{spl, block};
+            }
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_spl = saved_spl;
+    g_force_block = saved_block;
+    if (best.spl == 0) return RADIC_EDEVICE;
+    const int key_prec = kind == RADIC_WS_DET ? prec : (kind == RADIC_WS_INT ? 0 : prec);
+    const int km = kind == RADIC_WS_BATCHED ? 0 : m, kn = kind == RADIC_WS_BATCHED ? 0 : n;
+    g_tuned[std::make_tuple(kind, key_prec, km, kn)] = best;
+    if (hBest) {
+        hBest[0] = best.spl;
+        hBest[1] = best.block;
+    }
+    return RADIC_OK;
+}
+
+int radic_tune_save(const char* path) {
+    if (!path) return RADIC_EINVAL;
+    FILE* f = std::fopen(path, "w");
+    if (!f) return RADIC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    std::fprintf(f, "# radic launch-shape table v1: kind prec m n subsets_per_lane block\n");
+    for (const auto& kv : g_tuned)
+        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), kv.second.spl, kv.second.block);
+    return std::fclose(f) == 0 ? RADIC_OK : RADIC_EINVAL;
+}
+
+int radic_tune_load(const char* path) {
+    if (!path) return RADIC_EINVAL;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return RADIC_EINVAL;
+    std::map<std::tuple<int, int, int, int>, Shape> t;
+    char line[256];
+    int rc = RADIC_OK;
+    while (std::fgets(line, sizeof(line), f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        int k, p, m, n, spl, block;
+        if (std::sscanf(line, "%d %d %d %d %d %d", &k, &p, &m, &n, &spl, &block) != 6 || spl < 1 || spl > 4096 ||
+            block < kWave || block > kMaxBlock || block % kWave) {
+            rc = RADIC_EINVAL;
+            break;
+        }
+        t[std::make_tuple(k, p, m, n)] = Shape{spl, block};
+    }
+    std::fclose(f);
+    if (rc != RADIC_OK) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (const auto& kv : t) g_tuned[kv.first] = kv.second;
+    return RADIC_OK;
+}
 
 int radic_set_launch(int subsets_per_lane, int block_size) {
     if (subsets_per_lane < 0 || subsets_per_lane > 4096) return RADIC_EINVAL;

@@ -13,6 +13,7 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
+constexpr int kDeferCap = 32;        // per-wave global segment of minors to refactor in double
 
 // Per-workgroup partial of a floating-point enumeration (32 bytes).
 struct Partial {
@@ -45,6 +46,12 @@ struct FloatJob {
     DetHeader* header;
     double* terms;                // export mode: [count]
     unsigned char* cols;          // export mode: [count * m] or null
+    // FP32_BULK with deferral: per global wave, the number of queued minors and
+    // kDeferCap 16-byte entries; per workgroup, the double partials of the
+    // refactorisation kernel
+    unsigned* fb_count;
+    unsigned* fb_entries;
+    Partial* fb_partials;
 };
 
 // ---------------------------------------------------------------- arithmetic helpers

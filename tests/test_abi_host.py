@@ -163,3 +163,20 @@ def test_int_validation_without_device():
     assert L.radic_det_int_exact(fake, 13, 20, 20, mag, 8, ctypes.byref(ln), ctypes.byref(sg), fake, 1 << 24,
                                  nul) == radic.RADIC_ENOTSUP
     assert L.radic_workspace_bytes(radic.RADIC_WS_INT, 6, 40, 0) > 0
+
+
+def test_tune_table_roundtrip(tmp_path):
+    src = tmp_path / "in.txt"
+    src.write_text("# table\n0 0 8 32 4 128\n0 1 8 32 16 256\n1 0 6 40 8 64\n2 2 0 0 2 256\n")
+    radic.tune_load(src)
+    out = tmp_path / "out.txt"
+    radic.tune_save(out)
+    rows = [l.split() for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert ["0", "0", "8", "32", "4", "128"] in rows
+    assert ["2", "2", "0", "0", "2", "256"] in rows
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 0 8 32 4 96\n")          # block not a multiple of 64
+    with pytest.raises(radic.RadicError):
+        radic.tune_load(bad)
+    with pytest.raises(radic.RadicError):
+        radic.tune_load(tmp_path / "missing.txt")

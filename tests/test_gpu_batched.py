@@ -145,3 +145,16 @@ def test_workload5_sampled(precision):
         cands = [b for b, (k, A) in enumerate(batch) if k == kind]
         idx.append(max(cands, key=lambda b: math.comb(mats[b].shape[1], mats[b].shape[0])))
     check(mats, res, precision, idx)
+
+
+def test_autotune_batched_and_int():
+    print("[case] autotune batched", flush=True)
+    spl, block = radic.autotune(radic.RADIC_WS_BATCHED, precision="fp32_bulk")
+    assert spl >= 1 and block == 256
+    spl, block = radic.autotune(radic.RADIC_WS_BATCHED, precision="exact")
+    assert spl >= 1
+    spl, block = radic.autotune(radic.RADIC_WS_INT, 5, 12)
+    assert spl >= 1
+    mats = mixed_batch(30, seed=8)
+    res = radic.radic_det_batched(radic.Batch(mats), "fp32_bulk")
+    check(mats, res, "fp32_bulk")

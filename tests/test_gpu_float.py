@@ -215,6 +215,24 @@ def test_fallback_near_dependent_rows():
     print("error without fallback / S:", abs(bad["value"] - ref["value"]) / S)
 
 
+def test_fallback_overflow_in_some_workgroups():
+    # columns 1 and 2 nearly parallel: every minor holding both (the first
+    # C(18, 4) ranks of the dictionary order) is flagged, so the waves that own
+    # them overflow their deferral segment and their workgroups are redone in
+    # double, while the rest keep the float result plus a few deferred minors
+    rng = np.random.default_rng(34)
+    A = rng.standard_normal((6, 20))
+    A[:, 1] = A[:, 0] * (1.0 + 1e-7) + 1e-7 * rng.standard_normal(6)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, "fp32_bulk", "partial overflow 6x20")
+    assert math.comb(18, 4) <= got["n_fallback"] < math.comb(20, 6)
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-6, "partial overflow")
+    for spl, block in ((1, 64), (32, 256)):
+        radic.set_launch(spl, block)
+        got = run_case(A, "fp32_bulk", f"partial overflow spl={spl} block={block}")
+        assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-6, "partial overflow launch")
+
+
 def test_row_scaling_wide_range():
     # rows spanning ~1e+-30: float would overflow without the power-of-two row scaling
     rng = np.random.default_rng(41)
@@ -223,3 +241,14 @@ def test_row_scaling_wide_range():
     got = run_case(A, "fp32_bulk", "wide row scales")
     assert np.isfinite(got["value"])
     assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-5, "row scaling")
+
+
+def test_autotune_det_then_correct():
+    radic.set_launch(0, 0)
+    print("[case] autotune det 6x16", flush=True)
+    spl, block = radic.autotune(radic.RADIC_WS_DET, 6, 16, "fp64")
+    assert spl >= 1 and block in (64, 128, 256)
+    A = workloads.random_float(6, 16, seed=90)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, "fp64", "after autotune")
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-12, "autotuned")
