@@ -8,10 +8,11 @@ double-double accumulation).  Inputs are resident in device memory before the
 timed region; nothing is skipped inside it.
 
 Printed: one JSON line.  `value` is minors evaluated per second over the whole
-step (both forms); the per-form rates, errors against the oracle (normalised by
-sum |det(A_J)|), the roofline of the dominant kernel (HIP events recorded by the
-library around each enumeration launch inside the timed region) and the CPU
-oracle's rate on the host cores are reported beside it.
+step (both forms); the per-form rates (whole library call, events on the launch
+stream), errors against the oracle (normalised by sum |det(A_J)|), the roofline
+of the dominant kernel (HIP events recorded by the library around each
+enumeration launch inside the timed region) and the CPU oracle's rate on the
+host cores are reported beside it.
 """
 import argparse
 import json
@@ -28,6 +29,39 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 
 def counted_flops_per_minor(m):
     return 2.0 * m ** 3 / 3.0
+
+
+def gepp_flops(rows, cols, steps):
+    """Floating-point operations of `steps` steps of LU with partial pivoting on
+    a rows x cols block: per step k the multipliers (one multiply each), the
+    updates of the block's columns right of k (one FMA = 2 flops each) and one
+    reciprocal of the pivot."""
+    f = 0
+    for k in range(steps):
+        below = rows - 1 - k
+        f += below + 2 * below * (cols - 1 - k) + 1
+    return f
+
+
+def executed_flops(m, n, enumeration):
+    """Floating-point operations one launch performs on the whole C(n, m) rank
+    space.  Per minor: GEPP of the m x m minor (m - 1 steps; 2 sum t^2 + sum t +
+    (m - 1) = 315 for m = 8) plus the m - 1 multiplications of the pivot
+    product.  Prefix-shared (m >= 3): per prefix the m - 2 steps on the m x (m-2)
+    block, its 2 x (m-2) row solve for W, and the product of its pivots; per later
+    column W x (2m FMAs); per minor the 2 x 2 determinant and the product with
+    the prefix's signed pivot product (4 flops)."""
+    total = math.comb(n, m)
+    if enumeration == "per_minor" or m < 3:
+        return (gepp_flops(m, m, m - 1) + (m - 1)) * total
+    P = m - 2
+    per_prefix = gepp_flops(m, P, P) + 2 * P * (P - 1) + P
+    flops = 0
+    for v in range(P - 1, n - 2):            # last prefix column (0-based)
+        k = math.comb(v, P - 1)              # prefixes ending at v
+        r = n - 1 - v                        # columns after it
+        flops += k * (per_prefix + 4 * m * r + 4 * math.comb(r, 2))
+    return flops
 
 
 def cpu_baseline(A, threads, max_seconds=20.0):
@@ -50,12 +84,23 @@ def cpu_baseline(A, threads, max_seconds=20.0):
     return rates[len(rates) // 2], values[0], len(rates)
 
 
+def kernel_name(enumeration, form):
+    if enumeration == "per_minor":
+        return "k_radic_float<8,true,false,true>" if form == "fp32_bulk" else "k_radic_float<8,false,false,false>"
+    return "k_radic_shared<8,true>" if form == "fp32_bulk" else "k_radic_shared<8,false>"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared"],
+                    help="enumeration used by the library (default: auto, prefix-shared where supported)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="before the steps, run one plain device-to-device copy of this many bytes (a "
+                         "known-size reference for the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the rank-space split across "
@@ -75,15 +120,36 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     A = torch.from_numpy(A_host).to(dev)
+    radic.set_enumeration(args.enumeration)
     outs = {p: binding.new_f64_result(dev) for p in ("fp64", "fp32_bulk")}
     work = {p: binding.workspace(radic.RADIC_WS_DET, m, n, device=dev) for p in ("fp64", "fp32_bulk")}
     stream = torch.cuda.current_stream()
     print(f"[bench] workload 8x32, {total} minors, steps={args.steps} warmup={args.warmup}", file=sys.stderr,
           flush=True)
 
-    def step():
-        for p in ("fp64", "fp32_bulk"):
+    if args.copy_bytes > 0:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] reference copy of {src.numel() * 4} bytes done", file=sys.stderr, flush=True)
+        del src, dst
+
+    # events on the stream the library launches on (torch's current stream):
+    # per form, the whole call (enumeration, refactorisation, finalisation)
+    form_events = []
+
+    def step(record=False):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)] if record else None
+        if record:
+            ev[0].record(stream)
+        for i, p in enumerate(("fp64", "fp32_bulk")):
             radic.radic_det(A, precision=p, out=outs[p], work=work[p], sync=False)
+            if record:
+                ev[i + 1].record(stream)
+        if record:
+            form_events.append(ev)
 
     for _ in range(args.warmup):
         step()
@@ -93,7 +159,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        step(record=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     radic.profile_enable(False)
@@ -105,6 +171,8 @@ def main():
     k32 = launches[1::2]
     avg64 = sum(k64) / len(k64)
     avg32 = sum(k32) / len(k32)
+    call_ms = {"fp64": sum(e[0].elapsed_time(e[1]) for e in form_events) / len(form_events),
+               "fp32_bulk": sum(e[1].elapsed_time(e[2]) for e in form_events) / len(form_events)}
     res = {p: binding.read_f64_result(outs[p]) for p in outs}
 
     # CPU oracle: baseline rate and the reference value for the error figures
@@ -121,21 +189,24 @@ def main():
 
     S = ref["abs_sum"]
     flop = counted_flops_per_minor(m) * total
+    xflop = executed_flops(m, n, args.enumeration)
     per_form = {}
     for p, avg, peak in (("fp64", avg64, PEAK_FP64_TFLOPS), ("fp32_bulk", avg32, PEAK_FP32_TFLOPS)):
         r = res[p]
         per_form[p] = {
-            "subdet_per_s": total / (avg * 1e-3),
+            "subdet_per_s": total / (call_ms[p] * 1e-3),
+            "call_ms": call_ms[p],
             "kernel_ms": avg,
             "value": r["value"],
             "err_over_sum_abs": abs(r["value"] - ref["value"]) / S,
             "tol": 1e-12 if p == "fp64" else 1e-5,
             "n_fallback": r["n_fallback"],
-            "counted_tflops": flop / (avg * 1e-3) / 1e12,
+            "kernel_executed_tflops": xflop / (avg * 1e-3) / 1e12,
+            "kernel_counted_tflops": flop / (avg * 1e-3) / 1e12,
             "peak_tflops": peak,
         }
     dom = "fp64" if avg64 >= avg32 else "fp32_bulk"
-    achieved = per_form[dom]["counted_tflops"]
+    achieved = per_form[dom]["kernel_executed_tflops"]
     peak = per_form[dom]["peak_tflops"]
     line = {
         "metric": METRIC,
@@ -152,11 +223,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": "Radic determinant of one 8x32 float64 matrix, iid N(0,1), seed 150801328; "
                                "C(32,8)=10518300 minors per form; one step = FP64 form + FP32-bulk form",
-                   "m": m, "n": n, "minors_per_form": total, "forms": ["fp64", "fp32_bulk"]},
-        "roofline": {"bound": "alu", "kernel": f"k_radic_float<8,{'true' if dom == 'fp32_bulk' else 'false'},false>",
+                   "m": m, "n": n, "minors_per_form": total, "forms": ["fp64", "fp32_bulk"],
+                   "enumeration": args.enumeration},
+        "roofline": {"bound": "alu", "kernel": kernel_name(args.enumeration, dom),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": None,
-                     "per_unit": "counted (2/3) m^3 = 341.33 FLOP per minor x 10518300 minors per launch"},
+                     "per_unit": f"{xflop / total:.2f} executed FLOP per minor (averaged over the launch; "
+                                 f"{args.enumeration} enumeration) x {total} minors per launch = {xflop:.4g} FLOP; "
+                                 f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} FLOP per minor gives "
+                                 f"{per_form[dom]['kernel_counted_tflops']:.2f} TFLOP/s"},
         "cpu_baseline": cpu,
         "forms": per_form,
     }

@@ -243,6 +243,28 @@ int radic_set_launch(int subsets_per_lane, int block_size);
 int radic_set_fallback_tau(double tau);
 
 /*
+ * Which enumeration radic_det / radic_det_range use for float matrices.
+ *  RADIC_ENUM_AUTO            prefix-shared where supported (default).
+ *  RADIC_ENUM_PER_MINOR       every minor unranked/advanced and factored on its
+ *                             own by one lane (the scheme of Sections 4-6).
+ *  RADIC_ENUM_PREFIX_SHARED   the minors sharing their first m-2 columns (which
+ *                             the dictionary order of Section 3 makes
+ *                             consecutive) share the first m-2 steps of their
+ *                             LU with partial pivoting, whose pivots and
+ *                             multipliers depend on those columns only; each
+ *                             minor then costs its last two elimination steps.
+ *                             Used for 3 <= m <= 10 (FP64) or m <= 12
+ *                             (FP32_BULK); other shapes fall back to per-minor.
+ * Both give every minor's determinant (the terms of eq. (1)) individually; they
+ * differ in rounding only.  radic_det_subsets always uses per-minor.
+ * Returns RADIC_EINVAL for an unknown mode.
+ */
+#define RADIC_ENUM_AUTO 0
+#define RADIC_ENUM_PER_MINOR 1
+#define RADIC_ENUM_PREFIX_SHARED 2
+int radic_set_enumeration(int mode);
+
+/*
  * Timing hook for benchmarks: while enabled, the library records HIP events on
  * the launch stream around every launch of its main enumeration kernels.
  * radic_profile_read waits for them and returns the summed duration in ms and

@@ -30,6 +30,10 @@ RADIC_WS_DET = 0
 RADIC_WS_INT = 1
 RADIC_WS_BATCHED = 2
 
+RADIC_ENUM_AUTO = 0
+RADIC_ENUM_PER_MINOR = 1
+RADIC_ENUM_PREFIX_SHARED = 2
+
 RADIC_MAX_M = 12
 RADIC_MAX_N = 1024
 RADIC_MAX_PRIMES = 24
@@ -72,6 +76,7 @@ SIGNATURES = {
     "radic_tune_load": (_i, [ctypes.c_char_p]),
     "radic_set_launch": (_i, [_i, _i]),
     "radic_set_fallback_tau": (_i, [_d]),
+    "radic_set_enumeration": (_i, [_i]),
     "radic_profile_enable": (_i, [_i]),
     "radic_profile_read": (_i, [_dp, _ip]),
     "radic_profile_read_launches": (_i, [_dp, _i, _ip]),
@@ -268,6 +273,17 @@ def set_launch(subsets_per_lane=0, block_size=0):
 
 def set_fallback_tau(tau):
     _check(lib().radic_set_fallback_tau(float(tau)), "radic_set_fallback_tau")
+
+
+ENUMERATIONS = {"auto": RADIC_ENUM_AUTO, "per_minor": RADIC_ENUM_PER_MINOR,
+                "prefix_shared": RADIC_ENUM_PREFIX_SHARED}
+
+
+def set_enumeration(mode="auto"):
+    """Enumeration used by radic_det / radic_det_range: "auto", "per_minor" or
+    "prefix_shared" (or the RADIC_ENUM_* value)."""
+    code = ENUMERATIONS[mode] if isinstance(mode, str) else int(mode)
+    _check(lib().radic_set_enumeration(code), "radic_set_enumeration")
 
 
 def profile_enable(on=True):

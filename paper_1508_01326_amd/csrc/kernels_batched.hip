@@ -3,10 +3,11 @@
 //
 // The rank space [0, C(n_b, m_b)) of every matrix b is cut into chunks (the
 // granularity scheme of Section 5 applied to the whole batch).  A setup kernel
-// validates the descriptors and sizes the chunks, a one-workgroup scan turns the
-// per-matrix chunk counts into queue prefixes, and resident waves of two
-// persistent kernels (float matrices; exact int32 matrices) take chunk indices
-// from a global atomic counter until the queue is empty.  A wave that takes a
+// validates the descriptors, sizes the chunks and sorts the matrices into
+// classes by (type, m); a scan per class turns the per-matrix chunk counts into
+// queue prefixes, and one persistent kernel per class (compiled for that m, so
+// its register and LDS footprint is that of its own minors) takes chunk indices
+// from the class's global atomic counter until the queue is empty.  A wave that takes a
 // chunk of a matrix other than the one it holds stages that matrix in its own
 // LDS region, then runs the same per-lane enumeration and LU (or modular
 // elimination) as the single-matrix kernels.  Float chunks write their partial
@@ -308,18 +309,18 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
                 if (flag) {
                     const int pos = qcount + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-                    unsigned w[3];
+                    unsigned w[4];
                     pack_cols<M>(col, w);
                     L.queue[4 * pos + 0] = w[0];
                     L.queue[4 * pos + 1] = w[1];
                     L.queue[4 * pos + 2] = w[2];
-                    L.queue[4 * pos + 3] = 0u;
+                    L.queue[4 * pos + 3] = w[3];
                     nfb += 1;
                 }
                 qcount += __popcll(fm);
                 if (qcount > kFallbackCap - kWave) {
                     wave_lds_sync();
-                    refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab, [](int, double) {});
+                    refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab);
                     qcount = 0;
                 }
             }
@@ -328,7 +329,7 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
     }
     if (F32 && qcount > 0) {
         wave_lds_sync();
-        refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab, [](int, double) {});
+        refactor_queue_f64<M>(L.cd, L.queue, qcount, lane, hi, lo, ab);
     }
     wave_reduce_partial(hi, lo, ab, nfb);
     out = Partial{hi, lo, ab, nfb};

@@ -20,14 +20,10 @@
 // of Section 6), so results are bitwise reproducible for a given launch shape.
 #include <type_traits>
 
-#include "lu_float.h"
+#include "prefix.h"
+#include "stage.h"
 
 namespace radic {
-
-// Per-wave copy of the columns the lanes gather from, rows in the wave's order.
-template <int M, bool F32> __host__ __device__ int wave_copy_bytes(int n) {
-    return F32 ? align16(n * Layout<M>::st32 * 4) : align16(n * Layout<M>::st64 * 8);
-}
 
 // LDS per workgroup: binomial table, master copies of A (double; float for F32),
 // then per wave: its row-ordered copy and, with QUEUE (FP32 export), its
@@ -39,75 +35,18 @@ template <int M, bool F32, bool QUEUE> __host__ __device__ int lds_bytes(int n, 
     return b;
 }
 
-// Rewrite the wave's copy with rows in the order `perm` (copy row r = master row
-// perm[r]); the column-scale slot of the float layout is row independent.
-template <int M, typename T>
-__device__ void write_wave_copy(T* dst, const T* master, int stride, int n, unsigned long long perm, int lane,
-                                bool scale_slot) {
-    wave_lds_sync();
-    for (int e = lane; e < n * M; e += kWave) {
-        const int j = e / M, r = e - j * M;
-        const int src = (int)((perm >> (4 * r)) & 15ull);
-        dst[j * stride + r] = master[j * stride + src];
-    }
-    if (scale_slot)
-        for (int j = lane; j < n; j += kWave) dst[j * stride + M] = master[j * stride + M];
-    wave_lds_sync();
-}
-
-// ---------------------------------------------------------------- staging
-// Stage A column-major into LDS (double copy; for F32 also the row-scaled float
-// copy and the per-column scale).  Returns the workgroup-wide non-finite flag.
-// F32: rows scaled by 2^-e_i; WITH_F32: also write the float copy and its
-// reciprocal column scales.
-template <int M, bool F32, bool WITH_F32 = F32>
-__device__ int stage_matrix(const FloatJob& J, double* cd, float* cf, int* rowexp) {
-    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
-    const int n = J.n;
-    int bad = 0;
-    if (F32) {
-        // e_i: exponent of the row maximum, max|a_ij| = f 2^e_i with f in [0.5, 1)
-        if (threadIdx.x < M) {
-            const double* row = J.A + (long long)threadIdx.x * J.lda;
-            double mx = 0.0;
-            for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(row[j]));
-            int e = 0;
-            if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
-            rowexp[threadIdx.x] = e;
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < M * n; e += blockDim.x) {
-        int i = e / n, j = e - i * n;
-        double v = J.A[(long long)i * J.lda + j];
-        bad |= !isfinite(v);
-        if (F32) v = ldexp(v, -rowexp[i]);   // exact power-of-two scaling
-        cd[j * ST64 + i] = v;
-        if (WITH_F32) cf[j * ST32 + i] = (float)v;
-    }
-    bad = __syncthreads_or(bad);
-    if (WITH_F32) {
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            float s = 0.f;
-#pragma unroll
-            for (int i = 0; i < M; ++i) s = fmaxf(s, fabsf(cf[j * ST32 + i]));
-            cf[j * ST32 + M] = s > 0.f ? 1.0f / s : 0.f;   // reciprocal column scale 1/s_j
-        }
-        __syncthreads();
-    }
-    return bad;
-}
-
 // Refactor queued minors in double with the whole wave on one minor at a time
 // (LDS-resident, few registers); used when exporting FP32-bulk terms, where each
-// term must land at its own rank.  Lane 0 accumulates the terms.
+// term must land at its own rank.  The queue holds rank offsets, unranked here.
+// Lane 0 accumulates the terms.
 template <int M, bool EXPORT>
-__device__ void flush_fallback(const FloatJob& J, const double* cd, const unsigned* queue, int count, double* W,
-                               int lane, double& hi, double& lo, double& ab, int scale_exp) {
+__device__ void flush_fallback(const FloatJob& J, const unsigned long long* bt, const double* cd,
+                               const unsigned* queue, int count, double* W, int lane, double& hi, double& lo,
+                               double& ab, int scale_exp) {
     for (int e = 0; e < count; ++e) {
+        const unsigned off = queue[e];
         int c[M];
-        unpack_cols<M>(queue + 4 * e, c);
-        const unsigned off = queue[4 * e + 3];
+        unrank<M>(J.q_begin + off, J.n, bt, c);
         const double d = coop_det_f64<M>(cd, c, W, lane);
         const double term = radic_sign_odd<M>(c) ? -d : d;
         if (lane == 0) {
@@ -146,7 +85,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
     T* wcopy = reinterpret_cast<T*>(wr);
     unsigned char* fb = wr + wave_copy_bytes<M, F32>(n);
     unsigned* queue = reinterpret_cast<unsigned*>(fb);
-    double* W = reinterpret_cast<double*>(fb + kFallbackCap * 16);
+    double* W = reinterpret_cast<double*>(fb + kFallbackCap * 4);
 
     stage_binomials<M>(bt, n);
     const int bad = stage_matrix<M, F32>(J, cd, cf, rowexp);
@@ -227,18 +166,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
                     // whole workgroup in double
                     const int pos = gcount + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-                    if (flag && pos < kDeferCap) {
-                        unsigned w[3];
+                    if (flag && pos < J.defer_cap) {
+                        unsigned w[4];
                         pack_cols<M>(col, w);
-                        unsigned* ent = J.fb_entries + ((size_t)gwave * kDeferCap + pos) * 4;
+                        unsigned* ent = J.fb_entries + ((size_t)gwave * J.defer_cap + pos) * 4;
                         ent[0] = w[0];
                         ent[1] = w[1];
                         ent[2] = w[2];
-                        ent[3] = 0u;
+                        ent[3] = w[3];
                         nfb += 1;
                     }
                     gcount += __popcll(fm);
-                    if (gcount > kDeferCap) {
+                    if (gcount > J.defer_cap) {
                         overflow = true;
                         break;
                     }
@@ -250,18 +189,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
                     if (flag) {
                         const int pos = qcount + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(fm >> 32),
                                                      __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
-                        unsigned w[3];
-                        pack_cols<M>(col, w);
-                        queue[4 * pos + 0] = w[0];
-                        queue[4 * pos + 1] = w[1];
-                        queue[4 * pos + 2] = w[2];
-                        queue[4 * pos + 3] = (unsigned)(off0 + s);
+                        queue[pos] = (unsigned)(off0 + s);
                         nfb += 1;
                     }
                     qcount += __popcll(fm);
                     if (qcount > kFallbackCap - kWave) {
                         wave_lds_sync();
-                        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
+                        flush_fallback<M, EXPORT>(J, bt, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
                         qcount = 0;
                     }
                 }
@@ -272,10 +206,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_float(FloatJob J) {
     }
     if (QUEUE && qcount > 0) {
         wave_lds_sync();
-        flush_fallback<M, EXPORT>(J, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
+        flush_fallback<M, EXPORT>(J, bt, cd, queue, qcount, W, lane, hi, lo, ab, scale_exp);
     }
     if (EXPORT) return;
-    if (DEFER && lane == 0) J.fb_count[gwave] = (unsigned)gcount;   // above kDeferCap: overflowed
+    if (DEFER && lane == 0) J.fb_count[gwave] = (unsigned)gcount;   // above J.defer_cap: overflowed
 
     wave_reduce_partial(hi, lo, ab, nfb);
     if (lane == 0) {
@@ -336,40 +270,98 @@ __device__ void redo_wave_f64(const FloatJob& J, const unsigned long long* bt, c
     }
 }
 
-// Deferred refactorisation: every wave of the float launch queued its flagged
-// minors in a global segment; here one wave per segment refactors them in
-// double, one minor per lane, and each workgroup writes the partial of its
-// segments.  A workgroup with an overflowed segment instead redoes all of its
-// ranks in double and clears the float partial it replaces.  Segments are read
-// in wave order, so the sum is reproducible.
+// Deferred refactorisation.  Every wave of the float launch queued its flagged
+// minors in a global segment.  Workgroup j of this kernel takes the segments of
+// `R` consecutive float workgroups (R * waves <= 64 segments), concatenates them
+// and refactors the entries in double, one per lane, so that lanes stay busy
+// even though each segment holds only a few minors.  A float workgroup with an
+// overflowed segment is instead redone in double as a whole (its waves' rank
+// chunks, by the waves of this workgroup), and its float partial is cleared.
+// The entry-to-lane mapping is fixed, so the sum is reproducible.
 template <int M>
-__global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J) {
-    constexpr int ST64 = Layout<M>::st64;
+__global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J, int G, int R) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int rowexp[RADIC_MAX_M];
     __shared__ double red[4 * 16];
     __shared__ unsigned long long redn[16];
-    __shared__ int any, over;
+    __shared__ unsigned segoff[65];
+    __shared__ unsigned long long overmask;   // bit b: float workgroup fb0 + b overflowed
     const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
-    const int count = (int)J.fb_count[gwave];
-    if (threadIdx.x == 0) any = over = 0;
+    const int fb0 = blockIdx.x * R;
+    const int nb = min(R, G - fb0);
+    const int nseg = nb * waves;
+    if (threadIdx.x < 64) {
+        // wave 0: per-segment counts, the overflow mask and the exclusive prefix
+        // of the counts of segments in non-overflowed workgroups
+        const unsigned c = threadIdx.x < nseg ? J.fb_count[(size_t)fb0 * waves + threadIdx.x] : 0u;
+        const unsigned long long ov = __ballot(c > (unsigned)J.defer_cap);
+        unsigned long long om = 0;
+        for (int b = 0; b < nb; ++b)
+            if ((ov >> (b * waves)) & ((1ull << waves) - 1ull)) om |= 1ull << b;
+        const bool mine_over = threadIdx.x < nseg && ((om >> (threadIdx.x / waves)) & 1ull);
+        unsigned v = mine_over ? 0u : c;
+        // inclusive scan over the wave
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const unsigned u = __shfl_up(v, off, kWave);
+            if (lane >= off) v += u;
+        }
+        segoff[threadIdx.x + 1] = v;
+        if (threadIdx.x == 0) {
+            segoff[0] = 0;
+            overmask = om;
+        }
+    }
     __syncthreads();
-    if (lane == 0 && count > 0) atomicOr(&any, 1);
-    if (lane == 0 && count > kDeferCap) atomicOr(&over, 1);
-    __syncthreads();
+    const unsigned E = segoff[nseg];
+    const unsigned long long om = overmask;
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nfb = 0;
-    if (any) {
+    if (E > 0 || om) {
         unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
         double* cd = reinterpret_cast<double*>(smem + binom_bytes<M>(J.n));
-        if (over) stage_binomials<M>(bt, J.n);
+        if (om) stage_binomials<M>(bt, J.n);
         (void)stage_matrix<M, true, false>(J, cd, nullptr, rowexp);
-        if (over)
-            redo_wave_f64<M>(J, bt, cd, gwave, (unsigned long long)gridDim.x * waves, lane, hi, lo, ab, nfb);
-        else
-            refactor_queue_f64<M>(cd, J.fb_entries + gwave * kDeferCap * 4, count, lane, hi, lo, ab,
-                                  [](int, double) {});
+        for (int b = 0; b < nb; ++b) {
+            if (!((om >> b) & 1ull)) continue;
+            const unsigned long long gw = (unsigned long long)(fb0 + b) * waves + wave;
+            const unsigned long long nw = (unsigned long long)G * waves;
+            if (J.mapping == 0) {
+                redo_wave_f64<M>(J, bt, cd, gw, nw, lane, hi, lo, ab, nfb);
+            } else if constexpr (M >= 3) {
+                // the prefix blocks this wave of the float launch was given
+                const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+                for (unsigned long long blk = gw; blk < nblk; blk += nw) {
+                    unsigned long long r0, r1;
+                    prefix_block_ranks<M>(J, bt, blk, r0, r1);
+                    redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                }
+            }
+            if (threadIdx.x == 0) J.partials[fb0 + b] = Partial{0.0, 0.0, 0.0, 0ull};
+        }
+        for (unsigned base = (unsigned)wave * kWave; base < E; base += blockDim.x) {
+            const unsigned e = base + lane;
+            const bool valid = e < E;
+            const unsigned ee = valid ? e : base;
+            // segment holding entry ee: the last t with segoff[t] <= ee
+            int lo_s = 0, hi_s = nseg - 1;
+            while (lo_s < hi_s) {
+                const int mid = (lo_s + hi_s + 1) >> 1;
+                if (segoff[mid] <= ee) lo_s = mid;
+                else hi_s = mid - 1;
+            }
+            const unsigned pos = ee - segoff[lo_s];
+            const unsigned* ent = J.fb_entries + (((size_t)fb0 * waves + lo_s) * J.defer_cap + pos) * 4;
+            double ad;
+            const double term = refactor_entry_f64<M>(cd, ent, ad);
+            if (valid) {
+                double sum, err;
+                two_sum(hi, term, sum, err);
+                hi = sum;
+                lo += err;
+                ab += ad;
+            }
+        }
     }
     wave_reduce_partial(hi, lo, ab, nfb);
     if (lane == 0) {
@@ -388,55 +380,66 @@ __global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J) {
             nf += redn[w];
         }
         J.fb_partials[blockIdx.x] = Partial{h, l, a2, nf};
-        if (over) J.partials[blockIdx.x] = Partial{0.0, 0.0, 0.0, 0ull};
     }
 }
 
-// Fixed-order reduction of the workgroup partials into the result record.
-__global__ __launch_bounds__(256) void k_finalize_float(const Partial* parts, const Partial* fb_parts, int G,
-                                                        const DetHeader* h, radic_f64_result* out,
-                                                        unsigned long long count, int use_scale) {
-    __shared__ double sh[256], sl[256], sa[256];
-    __shared__ unsigned long long sn[256];
+// Fixed-order reduction of the workgroup partials (and of the refactorisation
+// partials) into the result record.  Each thread loads its partials in batches
+// of eight so that the loads overlap, then waves reduce by butterfly and wave
+// results are combined in wave order.
+__device__ __forceinline__ void add_partials(const Partial* parts, int G, double& hi, double& lo, double& ab,
+                                             unsigned long long& nf) {
+    constexpr int U = 8;
+    for (int base = threadIdx.x; base < G; base += U * blockDim.x) {
+        Partial p[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = base + k * blockDim.x;
+            p[k] = i < G ? parts[i] : Partial{0.0, 0.0, 0.0, 0ull};
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            dd_add(hi, lo, p[k].hi, p[k].lo);
+            ab += p[k].abs;
+            nf += p[k].nfb;
+        }
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2,
+                                                         const DetHeader* h, radic_f64_result* out,
+                                                         unsigned long long count, int use_scale) {
+    __shared__ double red[4 * 16];
+    __shared__ unsigned long long redn[16];
+    const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nf = 0;
-    for (int i = threadIdx.x; i < G; i += blockDim.x) {
-        Partial p = parts[i];
-        dd_add(hi, lo, p.hi, p.lo);
-        ab += p.abs;
-        nf += p.nfb;
-        if (fb_parts) {
-            const Partial q = fb_parts[i];
-            dd_add(hi, lo, q.hi, q.lo);
-            ab += q.abs;
-            nf += q.nfb;
-        }
+    add_partials(parts, G, hi, lo, ab, nf);
+    if (fb_parts) add_partials(fb_parts, G2, hi, lo, ab, nf);
+    wave_reduce_partial(hi, lo, ab, nf);
+    if (lane == 0) {
+        red[4 * wave + 0] = hi;
+        red[4 * wave + 1] = lo;
+        red[4 * wave + 2] = ab;
+        redn[wave] = nf;
     }
-    sh[threadIdx.x] = hi;
-    sl[threadIdx.x] = lo;
-    sa[threadIdx.x] = ab;
-    sn[threadIdx.x] = nf;
     __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            double a = sh[threadIdx.x], b = sl[threadIdx.x];
-            dd_add(a, b, sh[threadIdx.x + w], sl[threadIdx.x + w]);
-            sh[threadIdx.x] = a;
-            sl[threadIdx.x] = b;
-            sa[threadIdx.x] += sa[threadIdx.x + w];
-            sn[threadIdx.x] += sn[threadIdx.x + w];
-        }
-        __syncthreads();
-    }
     if (threadIdx.x == 0) {
+        double sh = red[0], sl = red[1], sa = red[2];
+        unsigned long long sn = redn[0];
+        for (int w = 1; w < waves; ++w) {
+            dd_add(sh, sl, red[4 * w + 0], red[4 * w + 1]);
+            sa += red[4 * w + 2];
+            sn += redn[w];
+        }
         const int e = use_scale ? h->scale_exp : 0;
         radic_f64_result r;
-        r.hi = ldexp(sh[0], e);
-        r.lo = ldexp(sl[0], e);
-        r.abs_sum = ldexp(sa[0], e);
+        r.hi = ldexp(sh, e);
+        r.lo = ldexp(sl, e);
+        r.abs_sum = ldexp(sa, e);
         r.value = r.hi + r.lo;
         r.n_subsets = count;
-        r.n_fallback = sn[0];
+        r.n_fallback = sn;
         r.status = h->nonfinite ? RADIC_ENONFINITE : RADIC_OK;
         r.reserved = 0;
         if (h->nonfinite) r.value = __builtin_nan("");
@@ -472,11 +475,21 @@ static hipError_t launch_dispatch(int m, const FloatJob& J, int grid, int block,
     }
 }
 
+// Float workgroups per refactorisation workgroup: as many as keep the
+// segments of one refactorisation workgroup within one wave's scan (64).
+int refactor_group(int block) { return kWave / (block / kWave); }
+
+int refactor_grid(int grid, int block) {
+    const int R = refactor_group(block);
+    return (grid + R - 1) / R;
+}
+
 template <int M>
 static hipError_t launch_refactor_m(const FloatJob& J, int grid, int block, hipStream_t s) {
     const int lds = binom_bytes<M>(J.n) + align16(J.n * Layout<M>::st64 * 8);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_refactor_deferred<M>, dim3(grid), dim3(block), lds, s, J);
+    hipLaunchKernelGGL(k_refactor_deferred<M>, dim3(refactor_grid(grid, block)), dim3(block), lds, s, J, grid,
+                       refactor_group(block));
     return hipGetLastError();
 }
 
@@ -510,10 +523,11 @@ hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, i
                         : launch_dispatch<false, false>(m, J, grid, block, s);
 }
 
-hipError_t launch_finalize_float(const Partial* parts, const Partial* fb_parts, int G, const DetHeader* h,
+hipError_t launch_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2, const DetHeader* h,
                                  radic_f64_result* out, unsigned long long count, int use_scale, hipStream_t s) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(256), 0, s, parts, fb_parts, G, h, out, count, use_scale);
+    hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(1024), 0, s, parts, G, fb_parts, G2, h, out, count,
+                       use_scale);
     return hipGetLastError();
 }
 

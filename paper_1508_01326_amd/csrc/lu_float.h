@@ -16,10 +16,10 @@ template <int M> struct Layout {
     static constexpr int st32 = 4 * g32;                  // floats per column (+1 slot: column scale)
 };
 
-// Per-wave fallback region: queue of 16-byte entries (packed columns, rank
-// offset) followed by the M x M double scratch of the wave-cooperative LU.
+// Per-wave fallback region of the export kernel: queue of rank offsets followed
+// by the M x M double scratch of the wave-cooperative LU.
 template <int M> __host__ __device__ constexpr int fallback_wave_bytes() {
-    return kFallbackCap * 16 + align16(M * M * 8);
+    return kFallbackCap * 4 + align16(M * M * 8);
 }
 
 // ---------------------------------------------------------------- LU building blocks
@@ -177,48 +177,58 @@ __device__ double coop_det_f64(const double* cd, const int (&c)[M], double* W, i
     return zero ? 0.0 : (neg ? -det : det);
 }
 
+// A queued minor is 16 bytes: its M 0-based column indices in 10-bit fields,
+// three per 32-bit word (M <= 12, n <= 1024).
+constexpr int kColBits = 10;
+
 template <int M>
-__device__ __forceinline__ void pack_cols(const int (&col)[M], unsigned (&w)[3]) {
-    w[0] = w[1] = w[2] = 0u;
+__device__ __forceinline__ void pack_cols(const int (&col)[M], unsigned (&w)[4]) {
+    w[0] = w[1] = w[2] = w[3] = 0u;
 #pragma unroll
-    for (int j = 0; j < M; ++j) w[j / 4] |= (unsigned)col[j] << (8 * (j % 4));
+    for (int j = 0; j < M; ++j) w[j / 3] |= (unsigned)col[j] << (kColBits * (j % 3));
 }
 
 template <int M>
 __device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
 #pragma unroll
-    for (int j = 0; j < M; ++j) col[j] = (w[j / 4] >> (8 * (j % 4))) & 0xFF;
+    for (int j = 0; j < M; ++j) col[j] = (w[j / 3] >> (kColBits * (j % 3))) & ((1u << kColBits) - 1u);
 }
 
-// Refactor queued minors in double, one minor per lane (rows in natural order,
-// from the row-scaled double copy cd); lane l takes entries l, l + 64, ...
-// Each lane adds its terms to its own double-double sum.  `on_term(entry, term)`
-// is called for every valid entry (export of individual terms).
-template <int M, typename OnTerm>
-__device__ void refactor_queue_f64(const double* cd, const unsigned* queue, int count, int lane, double& hi,
-                                   double& lo, double& ab, OnTerm on_term) {
+// Signed term of one queued minor refactored in double (rows in natural order,
+// from the row-scaled double copy cd).
+template <int M>
+__device__ __forceinline__ double refactor_entry_f64(const double* cd, const unsigned* entry, double& absdet) {
     constexpr int ST64 = Layout<M>::st64;
+    int c[M];
+    unpack_cols<M>(entry, c);
+    double a[M][M];
+    gather<M, double>(a, cd, ST64, c);
+    bool neg = radic_sign_odd<M>(c);
+    bool flag = false;
+    unsigned long long perm = 0;
+    int perm_odd = 0;
+    const double unused[M] = {};
+    const double d = lu_det<M, double, false>(a, neg, flag, unused, 0.0, perm, perm_odd);
+    absdet = fabs(d);
+    return neg ? -d : d;
+}
+
+// Refactor queued minors in double, one minor per lane; lane l takes entries
+// l, l + 64, ...  Each lane adds its terms to its own double-double sum.
+template <int M>
+__device__ void refactor_queue_f64(const double* cd, const unsigned* queue, int count, int lane, double& hi,
+                                   double& lo, double& ab) {
     for (int base = 0; base < count; base += kWave) {
         const int e = base + lane;
         const bool valid = e < count;
-        int c[M];
-        unpack_cols<M>(queue + 4 * (valid ? e : base), c);
-        double a[M][M];
-        gather<M, double>(a, cd, ST64, c);
-        bool neg = radic_sign_odd<M>(c);
-        bool flag = false;
-        unsigned long long perm = 0;
-        int perm_odd = 0;
-        const double unused[M] = {};
-        const double d = lu_det<M, double, false>(a, neg, flag, unused, 0.0, perm, perm_odd);
+        double ad;
+        const double term = refactor_entry_f64<M>(cd, queue + 4 * (valid ? e : base), ad);
         if (valid) {
-            const double term = neg ? -d : d;
             double s, err;
             two_sum(hi, term, s, err);
             hi = s;
             lo += err;
-            ab += fabs(d);
-            on_term(e, term);
+            ab += ad;
         }
     }
 }

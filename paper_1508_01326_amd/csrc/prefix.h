@@ -1,0 +1,96 @@
+// Prefix structure of the dictionary order used by the prefix-shared kernels.
+//
+// In the dictionary order of Section 3 all sequences that share their first
+// m-2 columns c_0 < ... < c_{m-3} (a "prefix") are consecutive: the pairs
+// (a, b), c_{m-3} < a < b < n, in dictionary order.  Prefixes are numbered in
+// the dictionary order of the (m-2)-subsets of the first n-2 columns (0-based),
+// so consecutive prefixes own consecutive rank ranges.  Waves take blocks of
+// kPrefixBlock consecutive prefixes.
+#pragma once
+
+#include "lu_float.h"
+
+namespace radic {
+
+constexpr int kPrefixBlock = 64;
+
+// Dictionary rank of the first sequence with prefix number pi, (c, c_{m-3}+1,
+// c_{m-3}+2); J.total when pi is past the last prefix.  Reads the LDS binomial
+// slice bt[x*M + y] = C(x, y).
+template <int M>
+__device__ unsigned long long first_completion_rank(unsigned long long pi, const FloatJob& J,
+                                                    const unsigned long long* bt) {
+    constexpr int P = M - 2;
+    if (pi >= J.n_prefix) return J.total;
+    const int n = J.n;
+    int c[P];
+    unrank_strided<P>(pi, n - 2, bt, M, c);
+    int full[M];
+#pragma unroll
+    for (int k = 0; k < P; ++k) full[k] = c[k];
+    full[P] = c[P - 1] + 1;
+    full[P + 1] = c[P - 1] + 2;
+    // the rank counts, place by place, the sequences skipped by every smaller
+    // value at that place (the inverse of the unranking of Section 4)
+    unsigned long long q = 0;
+    int prev = -1;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        for (int v = prev + 1; v < full[k]; ++v) q += bt[(n - 1 - v) * M + (M - 1 - k)];
+        prev = full[k];
+    }
+    return q;
+}
+
+// Ranks [lo, hi) owned by prefix block blk, clipped to the call's rank range.
+template <int M>
+__device__ void prefix_block_ranks(const FloatJob& J, const unsigned long long* bt, unsigned long long blk,
+                                   unsigned long long& lo, unsigned long long& hi) {
+    const unsigned long long pi0 = J.p_begin + blk * kPrefixBlock;
+    const unsigned long long pe = pi0 + kPrefixBlock;
+    const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
+    lo = first_completion_rank<M>(pi0, J, bt);
+    hi = first_completion_rank<M>(pi1, J, bt);
+    const unsigned long long qe = J.q_begin + J.count;
+    if (lo < J.q_begin) lo = J.q_begin;
+    if (hi > qe) hi = qe;
+    if (hi < lo) hi = lo;
+}
+
+// Every rank of [lo, hi) factored in double by the wave, minor by minor (rows in
+// natural order, from the row-scaled double copy cd): lane l takes the l-th of
+// 64 contiguous sub-ranges.  Counts the ranks in nvalid.
+template <int M>
+__device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
+                               unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
+                               double& ab, unsigned long long& nvalid) {
+    constexpr int ST64 = Layout<M>::st64;
+    if (hi <= lo) return;
+    const unsigned long long per = (hi - lo + kWave - 1) / kWave;
+    const unsigned long long s0 = lo + (unsigned long long)lane * per;
+    const unsigned long long s1 = s0 + per < hi ? s0 + per : hi;
+    const double none[M] = {};
+    int col[M];
+    unrank<M>(s0 < hi ? s0 : lo, J.n, bt, col);
+    for (unsigned long long s = 0; s < per; ++s) {
+        double a[M][M];
+        gather<M, double>(a, cd, ST64, col);
+        bool neg = radic_sign_odd<M>(col);
+        bool flag = false;
+        unsigned long long perm = 0;
+        int perm_odd = 0;
+        const double d = lu_det<M, double, false>(a, neg, flag, none, 0.0, perm, perm_odd);
+        if (s0 + s < s1) {
+            const double term = neg ? -d : d;
+            double sum, err;
+            two_sum(h, term, sum, err);
+            h = sum;
+            l += err;
+            ab += fabs(d);
+            nvalid += 1;
+        }
+        successor<M>(col, J.n);
+    }
+}
+
+}  // namespace radic

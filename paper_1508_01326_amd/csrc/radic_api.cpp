@@ -20,8 +20,9 @@
 namespace radic {
 
 hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, int grid, int block, hipStream_t s);
-hipError_t launch_finalize_float(const Partial* parts, const Partial* fb_parts, int G, const DetHeader* h,
+hipError_t launch_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2, const DetHeader* h,
                                  radic_f64_result* out, unsigned long long count, int use_scale, hipStream_t s);
+int refactor_grid(int grid, int block);
 hipError_t launch_refactor(int m, const FloatJob& J, int grid, int block, hipStream_t s);
 hipError_t launch_zero_result(radic_f64_result* out, hipStream_t s);
 hipError_t upload_binomials_float(const unsigned long long* host_table);
@@ -42,6 +43,9 @@ size_t int_result_offset();
 size_t int_result_size();
 int int_lds(int m, int n);
 int float_lds_bytes(int m, int n, int prec, int waves);
+hipError_t upload_binomials_shared(const unsigned long long* host_table);
+int shared_lds(int m, int n, int prec, int waves, int cap);
+hipError_t launch_shared(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s);
 
 constexpr int kBinomRows = RADIC_MAX_N + 1;
 constexpr int kBinomCols = 16;
@@ -145,6 +149,7 @@ static int ensure_device() {
     hipError_t ue = upload_binomials_float(t.data());
     if (ue == hipSuccess) ue = upload_binomials_int(t.data());
     if (ue == hipSuccess) ue = upload_binomials_batched(t.data());
+    if (ue == hipSuccess) ue = upload_binomials_shared(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
     return RADIC_OK;
@@ -157,6 +162,7 @@ struct Shape {
 };
 static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;   // (kind, prec, m, n) -> shape
 static int g_force_spl = 0, g_force_block = 0;
+static int g_enumeration = RADIC_ENUM_AUTO;
 static double g_tau = 1.0 / 1024.0;
 
 static Shape default_shape(int kind, int prec, int m, int n) {
@@ -206,13 +212,20 @@ struct ProfScope {
         if (!g_prof) return;
         a = take_event();
         b = take_event();
-        if (a) hipEventRecord(a, s);
+        if (a && b && hipEventRecord(a, s) == hipSuccess) return;
+        release();   // an unrecorded pair is not timed
     }
     ~ProfScope() {
         if (!a || !b) return;
-        hipEventRecord(b, s);
+        const bool ok = hipEventRecord(b, s) == hipSuccess;
         std::lock_guard<std::mutex> lk(g_mu);
-        g_prof_events.emplace_back(a, b);
+        if (ok) g_prof_events.emplace_back(a, b);
+        else release();
+    }
+    void release() {   // caller holds g_mu
+        if (a) g_event_pool.push_back(a);
+        if (b) g_event_pool.push_back(b);
+        a = b = nullptr;
     }
 };
 
@@ -223,12 +236,21 @@ static int check_workspace(void* ws, size_t bytes, size_t need) {
 }
 
 // Single-matrix workspace: header | partials[kMaxGrid] | refactor partials[kMaxGrid] |
-// per-wave segment counts [kMaxGrid*4] | per-wave segments [kMaxGrid*4][kDeferCap] (16 B entries)
+// per-wave segment counts [kMaxGrid*4] | deferral entries [kDeferEntries] (16 B each), split
+// evenly over the launch's waves
 static size_t ws_partials() { return kHeaderBytes; }
 static size_t ws_fb_partials() { return ws_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
 static size_t ws_fb_count() { return ws_fb_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
 static size_t ws_fb_entries() { return ws_fb_count() + sizeof(unsigned) * (size_t)kMaxGrid * 4; }
-static size_t det_workspace_bytes() { return ws_fb_entries() + 16 * (size_t)kMaxGrid * 4 * kDeferCap; }
+static size_t det_workspace_bytes() { return ws_fb_entries() + 16 * (size_t)kDeferEntries; }
+
+// Deferral entries per wave for a launch of `grid` workgroups of `block` threads.
+static int defer_cap_for(int grid, int block) {
+    const long long waves = (long long)grid * (block / kWave);
+    long long c = kDeferEntries / (waves > 0 ? waves : 1);
+    if (c > 4096) c = 4096;
+    return (int)c;
+}
 
 static int float_common_checks(const double* dA, int m, int n, long long lda, int prec) {
     if (!dA || m < 1 || n < 1 || lda < n) return RADIC_EINVAL;
@@ -260,6 +282,59 @@ static int grid_for(unsigned long long chunks, int block) {
     if (g > (unsigned long long)kMaxGrid) g = kMaxGrid;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+// Host unranking (Section 4) into 0-based columns.
+static void host_unrank0(int m, int n, unsigned long long q, int* cols) {
+    int c = 0;
+    for (int k = 0; k < m; ++k) {
+        for (;;) {
+            unsigned long long w = 0;
+            host_binomial(n - 1 - c, m - 1 - k, &w);
+            if (q < w) break;
+            q -= w;
+            ++c;
+        }
+        cols[k] = c++;
+    }
+}
+
+// Number of the prefix (first m-2 columns) of the sequence of rank q, in the
+// dictionary order of the (m-2)-subsets of the first n-2 columns.
+static unsigned long long host_prefix_index(int m, int n, unsigned long long q) {
+    int cols[RADIC_MAX_M];
+    host_unrank0(m, n, q, cols);
+    const int P = m - 2;
+    unsigned long long r = 0;
+    int prev = -1;
+    for (int k = 0; k < P; ++k) {
+        for (int v = prev + 1; v < cols[k]; ++v) {
+            unsigned long long w = 0;
+            host_binomial(n - 3 - v, P - 1 - k, &w);
+            r += w;
+        }
+        prev = cols[k];
+    }
+    return r;
+}
+
+// The prefix-shared kernels cover 3 <= m <= 12; FP64 stops at 10, where the
+// prefix block no longer fits the register file.
+static bool shared_eligible(int m, int prec) {
+    int mode;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        mode = g_enumeration;
+    }
+    if (mode == RADIC_ENUM_PER_MINOR) return false;
+    return m >= 3 && (prec == RADIC_FP32_BULK ? m <= 12 : m <= 10);
+}
+
+// Projected-column slots per wave: enough for one prefix of the widest kind.
+static int shared_cap(int m, int n, int prec) {
+    const int need = n - m + 2;
+    const int dflt = prec == RADIC_FP32_BULK ? 512 : 256;
+    return need > dflt ? need : dflt;
 }
 
 static int det_range_impl(const double* dA, int m, int n, long long lda, int prec, unsigned long long q_begin,
@@ -303,20 +378,43 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     J.fb_partials = reinterpret_cast<Partial*>(ws + ws_fb_partials());
     J.fb_count = reinterpret_cast<unsigned*>(ws + ws_fb_count());
     J.fb_entries = reinterpret_cast<unsigned*>(ws + ws_fb_entries());
-    const int grid = grid_for(J.chunks, sh.block);
+    J.total = total;
+    int grid = grid_for(J.chunks, sh.block);
+    bool shared = shared_eligible(m, prec);
+    if (shared) {
+        J.mapping = 1;
+        J.cap = shared_cap(m, n, prec);
+        host_binomial(n - 2, m - 2, &J.n_prefix);
+        J.p_begin = host_prefix_index(m, n, q_begin);
+        J.p_end = host_prefix_index(m, n, q_begin + count - 1) + 1;
+        int block = sh.block;
+        while (block > kWave && shared_lds(m, n, prec, block / kWave, J.cap) > kMaxLds) block -= kWave;
+        if (shared_lds(m, n, prec, block / kWave, J.cap) > kMaxLds) {
+            shared = false;
+            J.mapping = 0;
+        } else {
+            sh.block = block;
+            const unsigned long long blocks = (J.p_end - J.p_begin + 63) / 64;
+            const unsigned long long wpb = (unsigned long long)(block / kWave);
+            unsigned long long g = (blocks + wpb - 1) / wpb;
+            grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
+        }
+    }
     const bool defer = prec == RADIC_FP32_BULK;
+    J.defer_cap = defer_cap_for(grid, sh.block);
     hipError_t e;
     {
         ProfScope ps(stream);
-        e = launch_float(m, prec, false, J, grid, sh.block, stream);
+        e = shared ? launch_shared(m, prec, J, grid, sh.block, stream)
+                   : launch_float(m, prec, false, J, grid, sh.block, stream);
     }
     if (e != hipSuccess) return device_error("launch of the enumeration kernel", e);
     if (defer) {
         e = launch_refactor(m, J, grid, sh.block, stream);
         if (e != hipSuccess) return device_error("launch of the refactorisation kernel", e);
     }
-    e = launch_finalize_float(J.partials, defer ? J.fb_partials : nullptr, grid, J.header, dOut, count, defer,
-                              stream);
+    e = launch_finalize_float(J.partials, grid, defer ? J.fb_partials : nullptr, refactor_grid(grid, sh.block),
+                              J.header, dOut, count, defer, stream);
     return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
 }
 
@@ -851,6 +949,14 @@ int radic_host_unrank(int m, int n, uint64_t q, int* hCols) {
         hCols[k] = c + 1;
         ++c;
     }
+    return RADIC_OK;
+}
+
+int radic_set_enumeration(int mode) {
+    if (mode != RADIC_ENUM_AUTO && mode != RADIC_ENUM_PER_MINOR && mode != RADIC_ENUM_PREFIX_SHARED)
+        return RADIC_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_enumeration = mode;
     return RADIC_OK;
 }
 

@@ -13,7 +13,7 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
-constexpr int kDeferCap = 32;        // per-wave global segment of minors to refactor in double
+constexpr int kDeferEntries = 1 << 20;   // 16-byte deferral entries in a single-matrix workspace
 
 // Per-workgroup partial of a floating-point enumeration (32 bytes).
 struct Partial {
@@ -47,11 +47,21 @@ struct FloatJob {
     double* terms;                // export mode: [count]
     unsigned char* cols;          // export mode: [count * m] or null
     // FP32_BULK with deferral: per global wave, the number of queued minors and
-    // kDeferCap 16-byte entries; per workgroup, the double partials of the
+    // defer_cap 16-byte entries; per workgroup, the double partials of the
     // refactorisation kernel
+    int defer_cap;
     unsigned* fb_count;
     unsigned* fb_entries;
     Partial* fb_partials;
+    // Prefix-shared enumeration (m >= 3): the ranks are grouped by their first
+    // m-2 columns ("prefixes", numbered in dictionary order among the
+    // (m-2)-subsets of the first n-2 columns); waves take blocks of prefixes.
+    int mapping;                  // 0: lane chunks of ranks; 1: blocks of prefixes
+    int cap;                      // projected-column slots per wave (mapping 1)
+    unsigned long long total;     // C(n, m)
+    unsigned long long n_prefix;  // C(n-2, m-2)
+    unsigned long long p_begin;   // prefixes [p_begin, p_end) cover [q_begin, q_begin + count)
+    unsigned long long p_end;
 };
 
 // ---------------------------------------------------------------- arithmetic helpers
