@@ -84,6 +84,60 @@ def cpu_baseline(A, threads, max_seconds=20.0):
     return rates[len(rates) // 2], values[0], len(rates)
 
 
+def other_workloads(radic, binding, workloads, torch, dev, args):
+    """Secondary figures (not the headline): the exact-integer 6x40 workload and
+    the batched 4096-matrix workload, each timed with events around K calls
+    after warm-up, checked against the oracle (exact) or sampled oracle values."""
+    import numpy as np
+    import oracle
+    out = {}
+    # exact integer path: synchronous per call (the result comes back to the host)
+    A = workloads.single_matrix(3)
+    m, n = A.shape
+    total = math.comb(n, m)
+    dA = torch.from_numpy(A).to(dev)
+    work = binding.workspace(radic.RADIC_WS_INT, m, n, device=dev)
+    for _ in range(max(1, args.warmup)):
+        got = radic.radic_det_int_exact(dA, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        got = radic.radic_det_int_exact(dA, work=work)
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    out["exact_int_6x40"] = {"minors": total, "ms_per_call": ms, "subdet_per_s": total / (ms * 1e-3),
+                             "bit_exact_vs_oracle": got == oracle.radic_int(A),
+                             "note": "host-synchronous call including the 2 x 4-byte result copy"}
+    # batched: one graph launch over the 4096 matrices
+    mats = [M for _, M in workloads.batch_matrices()]
+    batch = radic.Batch(mats, device=dev)
+    g = radic.BatchGraph(batch, precision="fp32_bulk")
+    for _ in range(max(1, args.warmup)):
+        g.launch()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        g.launch()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    res = batch.results()
+    minors = sum(math.comb(M.shape[1], M.shape[0]) for M in mats)
+    bad = 0
+    for b in range(0, len(mats), 97):                 # sampled check against the oracle
+        M = mats[b]
+        if M.dtype == np.int32:
+            bad += res[b]["exact"] != oracle.radic_int(M)
+        else:
+            ref = oracle.radic_f64(M)
+            bad += abs(res[b]["value"] - ref["value"]) > 1e-5 * max(ref["abs_sum"], 1e-300)
+    out["batched_4096"] = {"minors": minors, "ms_per_launch": ms, "subdet_per_s": minors / (ms * 1e-3),
+                           "float_precision": "fp32_bulk", "sampled_mismatches": int(bad),
+                           "note": "one HIP-graph replay per launch; ints exact, floats FP32-bulk"}
+    return out
+
+
 def kernel_name(enumeration, form):
     if enumeration == "per_minor":
         return "k_radic_float<8,true,false,true>" if form == "fp32_bulk" else "k_radic_float<8,false,false,false>"
@@ -98,6 +152,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared"],
                     help="enumeration used by the library (default: auto, prefix-shared where supported)")
+    ap.add_argument("--other", action="store_true",
+                    help="also time the exact-integer workload (6x40 int32) and the batched workload "
+                         "(4096 mixed matrices, one HIP-graph launch); reported under other_workloads")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="before the steps, run one plain device-to-device copy of this many bytes (a "
                          "known-size reference for the HBM byte counters of a profiler run)")
@@ -235,6 +292,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": per_form,
     }
+    if args.other:
+        line["other_workloads"] = other_workloads(radic, binding, workloads, torch, dev, args)
     for p in per_form:
         if per_form[p]["err_over_sum_abs"] > per_form[p]["tol"]:
             print(f"[bench] ERROR: {p} error {per_form[p]['err_over_sum_abs']:.3e} above tolerance",

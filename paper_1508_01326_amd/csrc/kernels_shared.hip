@@ -13,8 +13,8 @@
 //     minor with that prefix).  From the multipliers it forms the two rows of
 //     the projection onto the two rows left after those steps, W = rows m-2 and
 //     m-1 of L^{-1} P.  It writes W x_c for every later column c (2 values per
-//     column) to its slot in the wave's LDS, with the signed product of the m-2
-//     pivots.
+//     column, the column read in the lane's row order) to its slot in the
+//     wave's LDS, with the signed product of the m-2 pivots.
 //  B. The wave's minors (the column pairs (a, b) after each prefix, in
 //     dictionary order) are split evenly over the 64 lanes.  Each minor is
 //     det(A_J) = (signed pivot product) * det([W x_a, W x_b]).  Its last two
@@ -91,36 +91,21 @@ __device__ __forceinline__ void gather_prefix(T (&a)[M][P], const T* base, int s
     }
 }
 
-// W x for one column x of the copy: the two values left in rows m-2, m-1 after
-// the prefix's elimination steps.
-template <int M, typename T>
-__device__ __forceinline__ void project(const T (&W0)[M], const T (&W1)[M], const T* src, T& t0, T& t1) {
+// The two values left in rows m-2, m-1 after the prefix's elimination steps,
+// for one column of the copy: with the lane's rows read in the lane's order
+// (copy row off[i] at position i), t_q = x_{m-2+q} + sum_{i<m-2} z_q[i] x_i,
+// z_q the rows m-2+q of -L21 L11^{-1}.
+template <int M, int P, typename T>
+__device__ __forceinline__ void project(const T (&z0)[P], const T (&z1)[P], const int (&off)[M], const T* src,
+                                        T& t0, T& t1) {
     T x[M];
-    if constexpr (sizeof(T) == 8) {
 #pragma unroll
-        for (int i = 0; i + 1 < M; i += 2) {
-            const double2 v = *reinterpret_cast<const double2*>(src + i);
-            x[i] = v.x;
-            x[i + 1] = v.y;
-        }
-        if (M & 1) x[M - 1] = src[M - 1];
-    } else {
+    for (int i = 0; i < M; ++i) x[i] = src[off[i]];
+    T s0 = x[P], s1 = x[P + 1];
 #pragma unroll
-        for (int i = 0; i + 3 < M; i += 4) {
-            const float4 v = *reinterpret_cast<const float4*>(src + i);
-            x[i] = v.x;
-            x[i + 1] = v.y;
-            x[i + 2] = v.z;
-            x[i + 3] = v.w;
-        }
-#pragma unroll
-        for (int i = (M / 4) * 4; i < M; ++i) x[i] = src[i];
-    }
-    T s0 = W0[0] * x[0], s1 = W1[0] * x[0];
-#pragma unroll
-    for (int o = 1; o < M; ++o) {
-        s0 = fma_t(W0[o], x[o], s0);
-        s1 = fma_t(W1[o], x[o], s1);
+    for (int i = 0; i < P; ++i) {
+        s0 = fma_t(z0[i], x[i], s0);
+        s1 = fma_t(z1[i], x[i], s1);
     }
     t0 = s0;
     t1 = s1;
@@ -318,33 +303,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                     z0[k] = s0;
                     z1[k] = s1;
                 }
-                // W in the copy's row order: lane position i holds copy row rel_i
-                T W0[M], W1[M];
+                // the lane's row order: position i holds copy row rel_i
+                int off[M];
 #pragma unroll
-                for (int o = 0; o < M; ++o) W0[o] = W1[o] = T(0);
-#pragma unroll
-                for (int i = 0; i < M; ++i) {
-                    T c0, c1;
-                    if (i < P) {
-                        c0 = z0[i < P ? i : 0];
-                        c1 = z1[i < P ? i : 0];
-                    } else {
-                        c0 = (i == P) ? T(1) : T(0);
-                        c1 = (i == P + 1) ? T(1) : T(0);
-                    }
-                    const int oi = (int)((rel >> (4 * i)) & 15ull);
-                    if (__ballot(oi != i) == 0) {
-                        W0[i] = c0;
-                        W1[i] = c1;
-                    } else {
-#pragma unroll
-                        for (int o = 0; o < M; ++o) {
-                            const bool h = (oi == o);
-                            W0[o] = h ? c0 : W0[o];
-                            W1[o] = h ? c1 : W1[o];
-                        }
-                    }
-                }
+                for (int i = 0; i < M; ++i) off[i] = (int)((rel >> (4 * i)) & 15ull);
                 // sign: row order (lane exchanges, copy order) and the prefix's share of (-1)^(r+s)
                 int ps = M * (M + 1) / 2 + P;
 #pragma unroll
@@ -371,7 +333,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                 for (int j = 0; j < rmax; ++j) {
                     const int col = min(c[P - 1] + 1 + j, n - 1);
                     T t0, t1;
-                    project<M, T>(W0, W1, wcopy + col * colstride, t0, t1);
+                    project<M, P, T>(z0, z1, off, wcopy + col * colstride, t0, t1);
                     if (take && j < r) {
                         T2 v;
                         v.x = t0;

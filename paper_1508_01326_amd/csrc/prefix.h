@@ -30,15 +30,12 @@ __device__ unsigned long long first_completion_rank(unsigned long long pi, const
     for (int k = 0; k < P; ++k) full[k] = c[k];
     full[P] = c[P - 1] + 1;
     full[P + 1] = c[P - 1] + 2;
-    // the rank counts, place by place, the sequences skipped by every smaller
-    // value at that place (the inverse of the unranking of Section 4)
-    unsigned long long q = 0;
-    int prev = -1;
+    // dictionary rank from the complement count: the sequences after `full`
+    // number sum_k C(n-1-c_k, M-k), read from the full binomial table
+    unsigned long long after = 0;
 #pragma unroll
-    for (int k = 0; k < M; ++k) {
-        for (int v = prev + 1; v < full[k]; ++v) q += bt[(n - 1 - v) * M + (M - 1 - k)];
-        prev = full[k];
-    }
+    for (int k = 0; k < M; ++k) after += g_binom[(n - 1 - full[k]) * kBinomCols + (M - k)];
+    const unsigned long long q = J.total - 1 - after;
     return q;
 }
 

@@ -13,7 +13,7 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
-constexpr int kDeferEntries = 1 << 20;   // 16-byte deferral entries in a single-matrix workspace
+constexpr int kDeferEntries = 1 << 22;   // 16-byte deferral entries in a single-matrix workspace
 
 // Per-workgroup partial of a floating-point enumeration (32 bytes).
 struct Partial {
