@@ -15,6 +15,7 @@ enumeration launch inside the timed region) and the CPU oracle's rate on the
 host cores are reported beside it.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -25,6 +26,24 @@ METRIC = "Radic subdeterminants/sec, m=8 n=32: FP64 vs FP32-bulk at stated error
 UNIT = "subdeterminants/s"
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP64 FMA per lane per clock
 PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked issue gives 78.6
+
+
+# HBM bytes per launch of the enumeration kernels on this workload, from
+# rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB reference copy (the
+# summary and commands are in profiles/k_radic_shared_8x32.md).  They hold for
+# the kernel sources they were taken on: `traffic` is reported only while the
+# sources hash to the same value.
+KERNEL_SOURCES = ["kernels_shared.hip", "prefix.h", "stage.h", "lu_float.h", "enumerate.h", "radic_internal.h"]
+PROFILED_TRAFFIC = {"sources_sha256": "bf65baf91d3976f4a6d7ce445ac65fe8ffa9f19be327a9351e2676a7aac442d6", "fp64": 458221, "fp32_bulk": 1497454}
+
+
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    base = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1508_01326_amd", "csrc")
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(base, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def counted_flops_per_minor(m):
@@ -136,6 +155,12 @@ def other_workloads(radic, binding, workloads, torch, dev, args):
                            "float_precision": "fp32_bulk", "sampled_mismatches": int(bad),
                            "note": "one HIP-graph replay per launch; ints exact, floats FP32-bulk"}
     return out
+
+
+def traffic_for(form, enumeration):
+    if enumeration == "per_minor" or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+        return None
+    return PROFILED_TRAFFIC[form]
 
 
 def kernel_name(enumeration, form):
@@ -284,7 +309,7 @@ def main():
                    "enumeration": args.enumeration},
         "roofline": {"bound": "alu", "kernel": kernel_name(args.enumeration, dom),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": traffic_for(dom, args.enumeration),
                      "per_unit": f"{xflop / total:.2f} executed FLOP per minor (averaged over the launch; "
                                  f"{args.enumeration} enumeration) x {total} minors per launch = {xflop:.4g} FLOP; "
                                  f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} FLOP per minor gives "
