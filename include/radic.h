@@ -256,7 +256,10 @@ int radic_set_fallback_tau(double tau);
  *                             Used for 3 <= m <= 10 (FP64) or m <= 12
  *                             (FP32_BULK); other shapes fall back to per-minor.
  * Both give every minor's determinant (the terms of eq. (1)) individually; they
- * differ in rounding only.  radic_det_subsets always uses per-minor.
+ * differ in rounding only.  radic_det_subsets always uses per-minor.  The same
+ * switch applies to radic_det_int_exact (prefix-shared for 3 <= m <= 10: the
+ * minors of a prefix share its fraction-free elimination steps modulo p; the
+ * result is the same exact integer either way).
  * Returns RADIC_EINVAL for an unknown mode.
  */
 #define RADIC_ENUM_AUTO 0

@@ -20,6 +20,7 @@
 
 #include "lu_float.h"
 #include "modp.h"
+#include "shared_int.h"
 
 namespace radic {
 
@@ -360,17 +361,51 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
 }
 
 // ---------------------------------------------------------------- exact chunks
+constexpr int kBatchCap = 256;   // projected-column slots per wave (prefix-shared exact chunks)
+
 template <int M> struct IntWaveLds {
     double cr[kBatchMaxN * IntLayout<M>::st];
+    IntSlot slot[M >= 3 && M <= 10 ? kPrefixBlock : 1];
+    unsigned incl[M >= 3 && M <= 10 ? kPrefixBlock : 1];
+    double2 tv[M >= 3 && M <= 10 ? kBatchCap : 1];
 };
 
 template <int M>
 __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const BatchMeta& mt, unsigned long long c,
-                          int b, IntWaveLds<M>& L, int lane, bool restage) {
+                          int b, IntWaveLds<M>& L, const unsigned long long* bt, int lane, bool restage) {
     constexpr int ST = IntLayout<M>::st;
     const int n = d.n;
     (void)restage;   // residues are restaged per prime
     const int* A = J.i32 + d.offset;
+    if constexpr (M >= 3 && M <= 10) {
+        // prefix-shared: the chunk's ranks [R0, R1), prefixes from the one holding R0
+        const unsigned long long R0 = c * mt.chunk;
+        const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
+        PrefixSpace sp;
+        sp.n = n;
+        sp.total = mt.total;
+        sp.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
+        const unsigned long long first = prefix_of_rank<M>(R0, n, bt, RADIC_MAX_M);
+        const unsigned long long rbase = first_completion_rank<M>(first, sp, bt, RADIC_MAX_M);
+        for (int pi = 0; pi < mt.n_primes; ++pi) {
+            const double p = g_prime[pi], pinv = g_prime_inv[pi];
+            wave_lds_sync();
+            for (int e = lane; e < M * n; e += kWave) {
+                const int i = e / n, j = e - i * n;
+                const double v = (double)A[(long long)i * d.lda + j];
+                const double q = __builtin_floor(v * pinv);
+                L.cr[j * ST + i] = mod_fix(__builtin_fma(-q, p, v), p);
+            }
+            wave_lds_sync();
+            double acc = 0.0;
+            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, rbase, R0, R1, p, pinv, kBatchCap,
+                                L.slot, L.incl, L.tv, lane, acc);
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);
+            if (lane == 0) atomicAdd(&J.residues[(size_t)b * RADIC_MAX_PRIMES + pi], (unsigned long long)acc);
+        }
+        return;
+    }
     const unsigned long long sub = mt.chunk / kWave;
     const unsigned long long q0 = c * mt.chunk + (unsigned long long)lane * sub;
     const int cnt = q0 < mt.total ? (int)((mt.total - q0) < sub ? (mt.total - q0) : sub) : 0;
@@ -425,6 +460,15 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
 template <int M>
 __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
     __shared__ IntWaveLds<M> lds[kBatchWaves];
+    // binomial table C(x, y), x < kBatchMaxN, y < RADIC_MAX_M, for the prefix walk
+    __shared__ unsigned long long bt[M >= 3 && M <= 10 ? kBatchMaxN * RADIC_MAX_M : 1];
+    if constexpr (M >= 3 && M <= 10) {
+        for (int e = threadIdx.x; e < kBatchMaxN * RADIC_MAX_M; e += blockDim.x) {
+            const int x = e / RADIC_MAX_M, y = e - x * RADIC_MAX_M;
+            bt[e] = g_binom[x * kBinomCols + y];
+        }
+        __syncthreads();
+    }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     IntWaveLds<M>& L = lds[wave];
     constexpr int cls = RADIC_MAX_M + M - 1;   // class_of(1, M)
@@ -440,7 +484,7 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
         const BatchMeta mt = J.meta[b];
         const bool restage = b != staged;
         staged = b;
-        int_chunk<M>(J, d, mt, c, b, L, lane, restage);
+        int_chunk<M>(J, d, mt, c, b, L, bt, lane, restage);
     }
 }
 

@@ -15,7 +15,7 @@
 // workgroup replaces all per-minor divisions.  Residues are held in doubles
 // (exact below 2^53) and multiplied with an error-free product and a floor-based
 // reduction (double products of 31-bit operands are split with an FMA).
-#include "modp.h"
+#include "shared_int.h"
 
 namespace radic {
 
@@ -157,6 +157,74 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int(IntJob J) {
     }
 }
 
+// ---------------------------------------------------------------- prefix-shared exact kernel
+struct IntSharedJob {
+    const int* A;
+    long long lda;
+    int n;
+    int cap;                      // projected-column slots per wave
+    int grid_x;
+    unsigned long long q_begin, count, total, n_prefix, p_begin, p_end;
+    double* partials;             // [prime][grid_x] residues
+};
+
+template <int M> __host__ __device__ int int_shared_lds_bytes(int n, int waves, int cap) {
+    return binom_bytes<M>(n) + align16(n * IntLayout<M>::st * 8) +
+           waves * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 4 + align16(cap * 16));
+}
+
+template <int M>
+__global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) {
+    constexpr int ST = IntLayout<M>::st;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[16];
+    const int n = J.n;
+    const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const double p = g_prime[blockIdx.y];
+    const double pinv = g_prime_inv[blockIdx.y];
+
+    unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
+    double* cr = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
+    unsigned char* wr = smem + binom_bytes<M>(n) + align16(n * ST * 8) +
+                        wave * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 4 + align16(J.cap * 16));
+    IntSlot* slot = reinterpret_cast<IntSlot*>(wr);
+    unsigned* incl = reinterpret_cast<unsigned*>(wr + kPrefixBlock * sizeof(IntSlot));
+    double2* tv = reinterpret_cast<double2*>(wr + kPrefixBlock * sizeof(IntSlot) + kPrefixBlock * 4);
+
+    stage_binomials<M>(bt, n);
+    for (int e = threadIdx.x; e < M * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        const double v = (double)J.A[(long long)i * J.lda + j];
+        const double q = __builtin_floor(v * pinv);
+        cr[j * ST + i] = mod_fix(__builtin_fma(-q, p, v), p);   // exact residue in [0, p)
+    }
+    __syncthreads();
+
+    double acc = 0.0;   // this lane's sum of signed minors mod p
+    const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+    const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
+    const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
+    for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
+        const unsigned long long next = J.p_begin + blk * kPrefixBlock;
+        const unsigned long long pe = next + kPrefixBlock;
+        const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
+        unsigned long long r0, r1;
+        prefix_block_ranks<M>(J, bt, blk, r0, r1);
+        const unsigned long long rbase = first_completion_rank<M>(next, J, bt);
+        int_prefix_range<M>(cr, n, bt, M, next, pi1, rbase, r0, r1, p, pinv, J.cap, slot, incl, tv, lane, acc);
+    }
+    // fixed-order sum over the wave, then waves in order
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = red[0];
+        for (int w = 1; w < waves; ++w) t = addmod(t, red[w], p);
+        J.partials[(long long)blockIdx.y * J.grid_x + blockIdx.x] = t;
+    }
+}
+
 // ---------------------------------------------------------------- CRT
 // Sum the workgroup residues per prime, then Garner's algorithm (mixed radix
 // digits v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
@@ -238,6 +306,46 @@ hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned l
     case MM: hipLaunchKernelGGL(k_radic_int<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J); break;
         RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
         RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
+#undef RADIC_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int int_shared_lds(int m, int n, int waves, int cap) {
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: return int_shared_lds_bytes<MM>(n, waves, cap);
+        RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6) RADIC_CASE(7) RADIC_CASE(8)
+        RADIC_CASE(9) RADIC_CASE(10)
+#undef RADIC_CASE
+        default: return 1 << 30;
+    }
+}
+
+hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
+                             unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
+                             hipStream_t s) {
+    IntSharedJob J{};
+    J.A = A;
+    J.lda = lda;
+    J.n = n;
+    J.cap = cap;
+    J.grid_x = grid_x;
+    J.q_begin = 0;
+    J.count = total;
+    J.total = total;
+    J.n_prefix = n_prefix;
+    J.p_begin = 0;
+    J.p_end = n_prefix;
+    J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
+    const int lds = int_shared_lds(m, n, block / kWave, cap);
+    (void)hipGetLastError();
+    switch (m) {
+#define RADIC_CASE(MM) \
+    case MM: hipLaunchKernelGGL(k_radic_int_shared<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J); break;
+        RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6) RADIC_CASE(7) RADIC_CASE(8)
+        RADIC_CASE(9) RADIC_CASE(10)
 #undef RADIC_CASE
         default: return hipErrorInvalidValue;
     }

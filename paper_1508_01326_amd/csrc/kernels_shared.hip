@@ -162,28 +162,6 @@ __device__ __forceinline__ void prefix_steps(T (&a)[M][P], double& prod, bool& n
     }
 }
 
-// Inclusive scan over the wave (lanes in order).
-__device__ __forceinline__ unsigned wave_scan_u32(unsigned v, int lane) {
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const unsigned u = __shfl_up(v, off, kWave);
-        if (lane >= off) v += u;
-    }
-    return v;
-}
-
-// Pair number x (dictionary order of the pairs ia < ib < r) to (ia, ib).
-__device__ __forceinline__ void unrank_pair(unsigned x, int r, int& ia, int& ib) {
-    const double b = 2.0 * r - 1.0;
-    int i = (int)((b - sqrt(b * b - 8.0 * (double)x)) * 0.5);
-    i = i < 0 ? 0 : (i > r - 2 ? r - 2 : i);
-    // row i starts at i (2r - i - 1) / 2; correct a rounding step either way
-    if ((unsigned)(i * (2 * r - i - 1) / 2) > x) --i;
-    if (i + 1 <= r - 2 && (unsigned)((i + 1) * (2 * r - i - 2) / 2) <= x) ++i;
-    ia = i;
-    ib = i + 1 + (int)(x - (unsigned)(i * (2 * r - i - 1) / 2));
-}
-
 template <int M, bool F32>
 __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     using T = typename std::conditional<F32, float, double>::type;

@@ -17,14 +17,14 @@ constexpr int kPrefixBlock = 64;
 // Dictionary rank of the first sequence with prefix number pi, (c, c_{m-3}+1,
 // c_{m-3}+2); J.total when pi is past the last prefix.  Reads the LDS binomial
 // slice bt[x*M + y] = C(x, y).
-template <int M>
-__device__ unsigned long long first_completion_rank(unsigned long long pi, const FloatJob& J,
-                                                    const unsigned long long* bt) {
+template <int M, class Job>
+__device__ unsigned long long first_completion_rank(unsigned long long pi, const Job& J,
+                                                    const unsigned long long* bt, int stride = M) {
     constexpr int P = M - 2;
     if (pi >= J.n_prefix) return J.total;
     const int n = J.n;
     int c[P];
-    unrank_strided<P>(pi, n - 2, bt, M, c);
+    unrank_strided<P>(pi, n - 2, bt, stride, c);
     int full[M];
 #pragma unroll
     for (int k = 0; k < P; ++k) full[k] = c[k];
@@ -39,9 +39,54 @@ __device__ unsigned long long first_completion_rank(unsigned long long pi, const
     return q;
 }
 
-// Ranks [lo, hi) owned by prefix block blk, clipped to the call's rank range.
+// Inclusive scan over the wave (lanes in order).
+__device__ __forceinline__ unsigned wave_scan_u32(unsigned v, int lane) {
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const unsigned u = __shfl_up(v, off, kWave);
+        if (lane >= off) v += u;
+    }
+    return v;
+}
+
+// Pair number x (dictionary order of the pairs ia < ib < r) to (ia, ib).
+__device__ __forceinline__ void unrank_pair(unsigned x, int r, int& ia, int& ib) {
+    const double b = 2.0 * r - 1.0;
+    int i = (int)((b - sqrt(b * b - 8.0 * (double)x)) * 0.5);
+    i = i < 0 ? 0 : (i > r - 2 ? r - 2 : i);
+    // row i starts at i (2r - i - 1) / 2; correct a rounding step either way
+    if ((unsigned)(i * (2 * r - i - 1) / 2) > x) --i;
+    if (i + 1 <= r - 2 && (unsigned)((i + 1) * (2 * r - i - 2) / 2) <= x) ++i;
+    ia = i;
+    ib = i + 1 + (int)(x - (unsigned)(i * (2 * r - i - 1) / 2));
+}
+
+// The rank space of one m x n matrix, for the prefix helpers.
+struct PrefixSpace {
+    int n;
+    unsigned long long total;      // C(n, m)
+    unsigned long long n_prefix;   // C(n-2, m-2)
+};
+
+// Number of the prefix of the sequence of rank q (bt[x*stride + y] = C(x, y)).
 template <int M>
-__device__ void prefix_block_ranks(const FloatJob& J, const unsigned long long* bt, unsigned long long blk,
+__device__ unsigned long long prefix_of_rank(unsigned long long q, int n, const unsigned long long* bt, int stride) {
+    constexpr int P = M - 2;
+    int c[M];
+    unrank_strided<M>(q, n, bt, stride, c);
+    unsigned long long pi = 0;
+    int prev = -1;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        for (int v = prev + 1; v < c[k]; ++v) pi += bt[(n - 3 - v) * stride + (P - 1 - k)];
+        prev = c[k];
+    }
+    return pi;
+}
+
+// Ranks [lo, hi) owned by prefix block blk, clipped to the call's rank range.
+template <int M, class Job>
+__device__ void prefix_block_ranks(const Job& J, const unsigned long long* bt, unsigned long long blk,
                                    unsigned long long& lo, unsigned long long& hi) {
     const unsigned long long pi0 = J.p_begin + blk * kPrefixBlock;
     const unsigned long long pe = pi0 + kPrefixBlock;

@@ -32,6 +32,10 @@ hipError_t launch_int_bound(const int* A, int m, int n, long long lda, void* ws,
 hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned long long count, int spl,
                            int grid_x, int n_primes, int block, void* ws, hipStream_t s);
 hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s);
+int int_shared_lds(int m, int n, int waves, int cap);
+hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
+                             unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
+                             hipStream_t s);
 size_t int_workspace_bytes();
 hipError_t upload_binomials_batched(const unsigned long long* t);
 hipError_t upload_primes_batched(const unsigned* primes, int count);
@@ -592,9 +596,31 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     if (hdr[1] != RADIC_OK) return RADIC_EOVERFLOW;
     const int k = hdr[0];
     // 2. residue sums per (workgroup, prime), 3. CRT
-    const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
-    const int grid = grid_for(chunks, sh.block);
+    int mode;
     {
+        std::lock_guard<std::mutex> lk(g_mu);
+        mode = g_enumeration;
+    }
+    const int cap = std::max(256, n - m + 2);
+    bool shared = mode != RADIC_ENUM_PER_MINOR && m >= 3 && m <= 10;
+    int block = sh.block;
+    if (shared) {
+        while (block > kWave && int_shared_lds(m, n, block / kWave, cap) > kMaxLds) block -= kWave;
+        shared = int_shared_lds(m, n, block / kWave, cap) <= kMaxLds;
+    }
+    int grid;
+    if (shared) {
+        unsigned long long n_prefix = 0;
+        host_binomial(n - 2, m - 2, &n_prefix);
+        const unsigned long long blocks = (n_prefix + 63) / 64;
+        const unsigned long long wpb = (unsigned long long)(block / kWave);
+        unsigned long long g = (blocks + wpb - 1) / wpb;
+        grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
+        ProfScope ps(stream);
+        e = launch_int_shared(dA, m, n, lda, total, n_prefix, cap, grid, k, block, dWork, stream);
+    } else {
+        const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
+        grid = grid_for(chunks, sh.block);
         ProfScope ps(stream);
         e = launch_int_main(dA, m, n, lda, total, sh.spl, grid, k, sh.block, dWork, stream);
     }

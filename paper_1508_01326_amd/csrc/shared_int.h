@@ -1,0 +1,280 @@
+// Prefix-shared exact elimination modulo a prime, shared by the single-matrix
+// and batched exact kernels.
+//
+// The minors with equal first m-2 columns (a prefix; consecutive in the
+// dictionary order of Section 3) share the first m-2 steps of their
+// fraction-free elimination modulo p: every step k multiplies the rows below
+// the pivot by the pivot u_k and subtracts multiples of the pivot row, and its
+// pivot (the first nonzero entry of column k) and multipliers depend on the
+// first k+1 columns only.  Per prefix a lane eliminates the m x (m-2) block
+// and forms the two rows W (2 x m) of the fraction-free elimination operator
+// that produce rows m-2, m-1; it writes t_c = W x_c mod p for every later
+// column c to LDS.  For a minor with later columns a < b,
+//     det = (t_a0 t_b1 - t_a1 t_b0) / prod_{k<m-2} P_k   (mod p),
+// P_k = u_0 ... u_k the running pivot products (the last two elimination steps
+// of the minor, written out), with the sign of the prefix's row exchanges.  The
+// denominators of the 64 prefixes of a round are inverted together (one Fermat
+// inverse per round, Montgomery's batch trick over the wave).  A prefix whose
+// block has a zero pivot column mod p makes all its minors 0 mod p.
+#pragma once
+
+#include "modp.h"
+#include "prefix.h"
+
+namespace radic {
+
+struct IntSlot {
+    double F;      // signed 1 / prod P_k mod p (0 if the prefix block is singular mod p)
+    int r;         // columns after the prefix
+    int toff;      // first projected-column slot
+    unsigned lo;   // first pair inside the call's rank range
+    int pad;
+};
+
+// sum_j w_j x_j mod p, the products reduced one by one and their sum (below
+// M p < 2^35, exact) once
+template <int M>
+__device__ __forceinline__ double dot_mod(const double (&w)[M], const double (&x)[M], double p, double pinv) {
+    double s = 0.0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) s += mulmod(w[j], x[j], p, pinv);
+    const double q = __builtin_floor(s * pinv);
+    return mod_fix(__builtin_fma(-q, p, s), p);
+}
+
+// Step K of the prefix's fraction-free elimination: pivot = first row >= K with
+// a nonzero entry; whole rows exchanged (the column-K entries below the pivot
+// are kept as the step's multipliers); the lane's row order tracked in rel.
+template <int M, int P, int K>
+__device__ __forceinline__ void int_prefix_steps(double (&a)[M][P], double (&u)[P], double p, double pinv,
+                                                 double& Pk, double& D, bool& zero, bool& neg,
+                                                 unsigned long long& rel) {
+    if constexpr (K < P) {
+        unsigned best = 0;
+#pragma unroll
+        for (int i = K; i < M; ++i) best = max(best, a[i][K] != 0.0 ? (unsigned)(15 - i) : 0u);
+        const bool col_zero = (best == 0u);
+        const int pr = col_zero ? K : 15 - (int)best;
+        zero |= col_zero;
+        neg ^= (pr != K);
+        if (__ballot(pr != K)) {
+            const unsigned long long x = ((rel >> (4 * K)) ^ (rel >> (4 * pr))) & 15ull;
+            rel ^= (x << (4 * K)) | (x << (4 * pr));
+#pragma unroll
+            for (int i = K + 1; i < M; ++i) {
+                const bool c = (pr == i);
+                if (__ballot(c)) {
+#pragma unroll
+                    for (int j = 0; j < P; ++j) {
+                        const double x0 = a[K][j], y0 = a[i][j];
+                        a[K][j] = c ? y0 : x0;
+                        a[i][j] = c ? x0 : y0;
+                    }
+                }
+            }
+        }
+        const double uk = col_zero ? 1.0 : a[K][K];
+        u[K] = uk;
+        Pk = mulmod(Pk, uk, p, pinv);
+        D = mulmod(D, Pk, p, pinv);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) {
+            const double l = a[i][K];
+#pragma unroll
+            for (int j = K + 1; j < P; ++j)
+                a[i][j] = submod(mulmod(uk, a[i][j], p, pinv), mulmod(l, a[K][j], p, pinv), p);
+        }
+        int_prefix_steps<M, P, K + 1>(a, u, p, pinv, Pk, D, zero, neg, rel);
+    }
+}
+
+// The signed minors mod p of the ranks [R0, R1) of one matrix whose residues
+// mod p are staged column-major in cr (stride IntLayout<M>::st), summed into
+// this lane's `acc`.  `next` is the prefix holding R0 and `rbase` the rank of its
+// first sequence; prefixes [next, pi1) are visited in rounds of up to 64 (one
+// per lane; while their later columns fit the cap projected-column slots).
+// bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform control flow throughout.
+template <int M>
+__device__ void int_prefix_range(const double* cr, int n, const unsigned long long* bt, int bstride,
+                                 unsigned long long next, unsigned long long pi1, unsigned long long rbase,
+                                 unsigned long long R0, unsigned long long R1, double p, double pinv, int cap,
+                                 IntSlot* slot, unsigned* incl, double2* tv, int lane, double& acc) {
+    constexpr int P = M - 2;
+    constexpr int ST = IntLayout<M>::st;
+    while (next < pi1 && rbase < R1) {
+        // lane l takes prefix next + l if it starts before R1 and its later
+        // columns still fit the projected-column slots (lane 0 always does)
+        const unsigned long long pi = next + lane;
+        const bool inb = pi < pi1;
+        int c[P];
+        unrank_strided<P>(inb ? pi : next, n - 2, bt, bstride, c);
+        const int r = n - 1 - c[P - 1];
+        const unsigned cfull = inb ? (unsigned)(r * (r - 1) / 2) : 0u;
+        const unsigned cscan = wave_scan_u32(cfull, lane);
+        const unsigned long long base = rbase + (cscan - cfull);
+        const bool have = inb && base < R1;
+        const unsigned rs = wave_scan_u32(have ? (unsigned)r : 0u, lane);
+        const bool take = have && rs <= (unsigned)cap;
+        const int ntake = __popcll(__ballot(take));
+        const unsigned round_total = __shfl(cscan, ntake - 1, kWave);
+        const unsigned cnt = take ? cfull : 0u;
+        unsigned lo_c = 0, hi_c = cnt;
+        if (base < R0) {
+            const unsigned long long d = R0 - base;
+            lo_c = d < cnt ? (unsigned)d : cnt;
+        }
+        if (base + cnt > R1) {
+            const unsigned long long d = R1 > base ? R1 - base : 0ull;
+            hi_c = d < cnt ? (unsigned)d : cnt;
+        }
+        if (hi_c < lo_c) hi_c = lo_c;
+        const unsigned cc = hi_c - lo_c;
+        const unsigned ccincl = wave_scan_u32(cc, lane);
+        const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);
+
+        // ---------------- phase A: the prefix's m-2 fraction-free steps
+        {
+            double a[M][P];
+#pragma unroll
+            for (int j = 0; j < P; ++j)
+#pragma unroll
+                for (int i = 0; i < M; ++i) a[i][j] = cr[c[j] * ST + i];
+            double u[P];
+            unsigned long long rel = 0;
+#pragma unroll
+            for (int q = 0; q < M; ++q) rel |= (unsigned long long)q << (4 * q);
+            double Pk = 1.0, D = 1.0;
+            bool zero = false, neg = false;
+            int_prefix_steps<M, P, 0>(a, u, p, pinv, Pk, D, zero, neg, rel);
+            // W rows m-2, m-1 of the elimination operator, by the backward
+            // recurrence w <- w E_k (E_k: rows > k scaled by u_k, minus
+            // multiples of row k)
+            double w0[M], w1[M];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                w0[j] = (j == P) ? 1.0 : 0.0;
+                w1[j] = (j == P + 1) ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int k = P - 1; k >= 0; --k) {
+                double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+                for (int i = k + 1; i < M; ++i) {
+                    d0 += mulmod(w0[i], a[i][k], p, pinv);
+                    d1 += mulmod(w1[i], a[i][k], p, pinv);
+                }
+                d0 = mod_fix(__builtin_fma(-__builtin_floor(d0 * pinv), p, d0), p);
+                d1 = mod_fix(__builtin_fma(-__builtin_floor(d1 * pinv), p, d1), p);
+#pragma unroll
+                for (int j = k + 1; j < M; ++j) {
+                    w0[j] = mulmod(w0[j], u[k], p, pinv);
+                    w1[j] = mulmod(w1[j], u[k], p, pinv);
+                }
+                w0[k] = submod(w0[k], d0, p);
+                w1[k] = submod(w1[k], d1, p);
+            }
+            // 1 / D for every prefix of the round: Montgomery's batch inversion
+            // over the wave (prefix products, one inverse, suffix products)
+            const double Dz = (take && !zero) ? D : 1.0;
+            double pre = Dz;   // inclusive prefix product
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const double v = __shfl_up(pre, off, kWave);
+                if (lane >= off) pre = mulmod(pre, v, p, pinv);
+            }
+            double suf = Dz;   // inclusive suffix product
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const double v = __shfl_down(suf, off, kWave);
+                if (lane + off < kWave) suf = mulmod(suf, v, p, pinv);
+            }
+            const double total = __shfl(pre, kWave - 1, kWave);
+            const double tinv = invmod(total, p, pinv);
+            const double before = __shfl_up(pre, 1, kWave);
+            const double after = __shfl_down(suf, 1, kWave);
+            double inv = tinv;
+            if (lane > 0) inv = mulmod(inv, before, p, pinv);
+            if (lane < kWave - 1) inv = mulmod(inv, after, p, pinv);
+            // sign: prefix row exchanges and the prefix's share of (-1)^(r+s);
+            // the pair (a, b) adds 2 (n - r + 1) + its offsets
+            int ps = M * (M + 1) / 2 + P;
+#pragma unroll
+            for (int k = 0; k < P; ++k) ps += c[k];
+            const bool sg = neg ^ ((ps & 1) != 0);
+            double F = zero ? 0.0 : inv;
+            if (sg && F != 0.0) F = p - F;
+            int off[M];
+#pragma unroll
+            for (int i = 0; i < M; ++i) off[i] = (int)((rel >> (4 * i)) & 15ull);
+            const int toff = (int)rs - r;
+            if (take) {
+                IntSlot sl;
+                sl.F = F;
+                sl.r = r;
+                sl.toff = toff;
+                sl.lo = lo_c;
+                sl.pad = 0;
+                slot[lane] = sl;
+                incl[lane] = ccincl;
+            }
+            int rmax = take ? r : 0;
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) rmax = max(rmax, __shfl_xor(rmax, o, kWave));
+            for (int j = 0; j < rmax; ++j) {
+                const int col = min(c[P - 1] + 1 + j, n - 1);
+                double x[M];
+#pragma unroll
+                for (int i = 0; i < M; ++i) x[i] = cr[col * ST + off[i]];
+                const double t0 = dot_mod<M>(w0, x, p, pinv), t1 = dot_mod<M>(w1, x, p, pinv);
+                if (take && j < r) tv[toff + j] = make_double2(t0, t1);
+            }
+        }
+        wave_lds_sync();
+
+        // ---------------- phase B: the round's minors, split evenly over the lanes
+        const unsigned chunk = (Tr + kWave - 1) / kWave;
+        if (chunk > 0) {
+            const unsigned g0 = (unsigned)lane * chunk;
+            const unsigned gend = min(g0 + chunk, Tr);
+            const bool active = g0 < Tr;
+            int s = 0;
+            {
+                int l2 = 0, h2 = ntake - 1;
+                while (l2 < h2) {
+                    const int mid = (l2 + h2) >> 1;
+                    if (incl[mid] > g0) h2 = mid;
+                    else l2 = mid + 1;
+                }
+                s = active ? l2 : 0;
+            }
+            IntSlot h = slot[s];
+            int ia = 0, ib = 1;
+            if (active) unrank_pair(g0 - (s > 0 ? incl[s - 1] : 0u) + h.lo, h.r, ia, ib);
+            double2 ta = tv[h.toff + ia];
+            for (unsigned k = 0; k < chunk; ++k) {
+                const bool valid = g0 + k < gend;
+                const double2 tb = tv[h.toff + ib];
+                const double cross = submod(mulmod(ta.x, tb.y, p, pinv), mulmod(ta.y, tb.x, p, pinv), p);
+                double term = mulmod(h.F, cross, p, pinv);
+                if (((ia + ib) & 1) && term != 0.0) term = p - term;
+                if (valid) acc = addmod(acc, term, p);
+                if (++ib >= h.r) {
+                    ++ia;
+                    ib = ia + 1;
+                    if (ib >= h.r) {
+                        s = min(s + 1, ntake - 1);
+                        h = slot[s];
+                        ia = 0;
+                        ib = 1;
+                    }
+                    ta = tv[h.toff + ia];
+                }
+            }
+        }
+        rbase += round_total;
+        next += (unsigned long long)ntake;
+        wave_lds_sync();
+    }
+}
+
+}  // namespace radic

@@ -101,3 +101,26 @@ def test_capacity_too_small():
         assert rc == radic.RADIC_EOVERFLOW and ln.value == need
     else:
         assert rc == radic.RADIC_OK
+
+
+@pytest.mark.parametrize("mode", ["per_minor", "prefix_shared"])
+def test_enumerations_bit_exact(mode):
+    # the prefix-shared exact kernel (minors sharing their first m-2 columns share
+    # those fraction-free elimination steps mod p) and the per-minor kernel
+    radic.set_enumeration(mode)
+    try:
+        for m, n, seed in [(3, 60, 1), (4, 9, 5), (5, 22, 2), (8, 16, 3), (10, 14, 4), (10, 10, 6)]:
+            A = workloads.random_int(m, n, seed=900 + seed, lo=-1000, hi=1000)
+            assert run_int(A, f"{mode} {m}x{n}") == oracle.radic_int(A)
+    finally:
+        radic.set_enumeration("auto")
+
+
+def test_shared_exact_rank_deficient_prefixes():
+    # repeated and zero columns make whole prefix blocks singular mod every prime
+    rng = np.random.default_rng(77)
+    A = rng.integers(-20, 21, size=(6, 18)).astype(np.int32)
+    A[:, 3] = A[:, 1]
+    A[:, 7] = 0
+    A[:, 12] = 2 * A[:, 5]
+    assert run_int(A, "singular prefixes") == oracle.radic_int(A)
