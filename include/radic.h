@@ -175,6 +175,25 @@ int radic_det_subsets(const double *dA, int m, int n, int64_t lda, int prec, uin
                       uint64_t count, double *dTerms, uint8_t *dCols, hipStream_t stream);
 
 /*
+ * radic_det_2xn -- Radic determinant of a 2 x n float64 matrix in O(n), the
+ * two-row case the paper's introduction cites: with u_j = (-1)^j a_1j and
+ * v_j = (-1)^j a_2j, eq. (1) with r = 3 is -sum_k (U_{k-1} v_k - V_{k-1} u_k),
+ * U, V the prefix sums.  Runs of columns are combined in column order in
+ * double-double arithmetic.  n may exceed RADIC_MAX_N (any n >= 1 whose 2 x n
+ * input fits in memory).
+ *   dA     device, 2 x n float64, row-major, leading dimension lda >= n.
+ *   dOut   device, one radic_f64_result: value/hi/lo as in radic_det; abs_sum
+ *          holds the O(n) upper bound sum_{j<k} (|u_j||v_k| + |u_k||v_j|) on
+ *          sum |det(A_J)| (the exact sum of absolute minors needs every pair);
+ *          n_subsets = n(n-1)/2, n_fallback = 0.
+ *   dWork  device workspace of at least radic_workspace_bytes(RADIC_WS_DET, 2, n, 0).
+ * Asynchronous.  n = 1 writes 0 (m > n).  Errors: EINVAL (null pointers, n < 1,
+ * lda < n), EWORKSPACE, EDEVICE; non-finite entries give status ENONFINITE.
+ */
+int radic_det_2xn(const double *dA, int64_t n, int64_t lda, radic_f64_result *dOut, void *dWork,
+                  size_t work_bytes, hipStream_t stream);
+
+/*
  * radic_det_int_exact -- exact Radic determinant of one int32 matrix.
  * Each minor is eliminated fraction-free modulo k 31-bit primes (k chosen on the
  * device from a Hadamard-type bound so that the product of the primes exceeds

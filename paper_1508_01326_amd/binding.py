@@ -77,6 +77,7 @@ SIGNATURES = {
     "radic_set_launch": (_i, [_i, _i]),
     "radic_set_fallback_tau": (_i, [_d]),
     "radic_set_enumeration": (_i, [_i]),
+    "radic_det_2xn": (_i, [_vp, _i64, _i64, _vp, _vp, _sz, _vp]),
     "radic_profile_enable": (_i, [_i]),
     "radic_profile_read": (_i, [_dp, _ip]),
     "radic_profile_read_launches": (_i, [_dp, _i, _ip]),
@@ -193,6 +194,25 @@ def radic_det(A, precision="fp64", out=None, work=None, stream=None, sync=True):
     if not sync:
         return out
     torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+    return read_f64_result(out)
+
+
+def radic_det_2xn(A, out=None, work=None, stream=None, sync=True):
+    """O(n) Radic determinant of a 2 x n float64 CUDA matrix; abs_sum in the
+    result is an upper bound on sum |det(A_J)| (see include/radic.h)."""
+    torch = _torch()
+    _require_cuda(A, torch.float64, "A")
+    if A.dim() != 2 or A.shape[0] != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2 x n matrix with unit column stride")
+    n, lda = A.shape[1], A.stride(0)
+    out = out if out is not None else new_f64_result(A.device)
+    work = work if work is not None else workspace(RADIC_WS_DET, 2, 2, device=A.device)
+    rc = lib().radic_det_2xn(ctypes.c_void_p(A.data_ptr()), n, lda, ctypes.c_void_p(out.data_ptr()),
+                             ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_handle(stream))
+    _check(rc, "radic_det_2xn")
+    if not sync:
+        return out
+    torch.cuda.synchronize(A.device)
     return read_f64_result(out)
 
 

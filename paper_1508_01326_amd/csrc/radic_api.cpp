@@ -33,6 +33,9 @@ hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned l
                            int grid_x, int n_primes, int block, void* ws, hipStream_t s);
 hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s);
 int int_shared_lds(int m, int n, int waves, int cap);
+size_t run_bytes();
+hipError_t launch_2xn(const double* A, long long lda, long long n, int G, void* runs, void* flag,
+                      radic_f64_result* out, hipStream_t s);
 hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
                              unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
                              hipStream_t s);
@@ -565,6 +568,25 @@ int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uin
     const int grid = grid_for(J.chunks, sh.block);
     hipError_t e = launch_float(m, prec, true, J, grid, sh.block, stream);
     return e == hipSuccess ? RADIC_OK : device_error("launch of the export kernel", e);
+}
+
+int radic_det_2xn(const double* dA, int64_t n, int64_t lda, radic_f64_result* dOut, void* dWork, size_t work_bytes,
+                  hipStream_t stream) {
+    if (!dA || !dOut || n < 1 || lda < n) return RADIC_EINVAL;
+    int rc = check_workspace(dWork, work_bytes, det_workspace_bytes());
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    if (n < 2) return zero_result(dOut, stream);   // m = 2 > n: zero (Definition 3)
+    long long G = (n + 4095) / 4096;
+    if (G > kMaxGrid) G = kMaxGrid;
+    if ((size_t)G * run_bytes() > 16 * (size_t)kDeferEntries) return RADIC_ENOTSUP;
+    unsigned char* ws = static_cast<unsigned char*>(dWork);
+    hipError_t e;
+    {
+        ProfScope ps(stream);
+        e = launch_2xn(dA, (long long)lda, (long long)n, (int)G, ws + ws_fb_entries(), ws, dOut, stream);
+    }
+    return e == hipSuccess ? RADIC_OK : device_error("launch of the two-row kernels", e);
 }
 
 int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* hMag, int mag_capacity,

@@ -92,6 +92,11 @@ def test_argument_validation_without_device():
                        nul) == radic.RADIC_ENOTSUP
     # export mode needs an output
     assert L.radic_det_subsets(fake, 2, 3, 3, 0, 0, 1, nul, nul, nul) == radic.RADIC_EINVAL
+    # two-row path: n >= 1, lda >= n, pointers
+    assert L.radic_det_2xn(nul, 5, 5, fake, fake, 1 << 30, nul) == radic.RADIC_EINVAL
+    assert L.radic_det_2xn(fake, 0, 5, fake, fake, 1 << 30, nul) == radic.RADIC_EINVAL
+    assert L.radic_det_2xn(fake, 5, 4, fake, fake, 1 << 30, nul) == radic.RADIC_EINVAL
+    assert L.radic_det_2xn(fake, 5, 5, fake, fake, 16, nul) == radic.RADIC_EWORKSPACE
 
 
 def test_launch_and_tau_setters_validate():
