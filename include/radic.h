@@ -30,7 +30,8 @@
  *    including the device-detected status, is valid once the stream reaches
  *    that point.  Nothing here uses stream priorities.
  *  - Return values are radic_status codes for host-detected conditions.
- *  - Limits: 1 <= m <= RADIC_MAX_M, n <= RADIC_MAX_N, C(n, m) < 2^63.
+ *  - Limits: 1 <= m <= RADIC_MAX_M (RADIC_MAX_M_WIDE for radic_det and
+ *    radic_det_range), n <= RADIC_MAX_N, C(n, m) < 2^63.
  */
 #ifndef RADIC_H
 #define RADIC_H
@@ -45,6 +46,11 @@ extern "C" {
 #endif
 
 #define RADIC_MAX_M 12
+/* radic_det / radic_det_range also take 12 < m <= RADIC_MAX_M_WIDE: such minors
+ * are factored by a group of 32 lanes each (one row per lane, partial pivoting
+ * by a group max-reduction, true division), in double for both precisions
+ * (FP32_BULK reports n_fallback = 0). */
+#define RADIC_MAX_M_WIDE 32
 #define RADIC_MAX_N 1024
 #define RADIC_MAX_PRIMES 24
 

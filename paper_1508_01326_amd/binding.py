@@ -35,6 +35,7 @@ RADIC_ENUM_PER_MINOR = 1
 RADIC_ENUM_PREFIX_SHARED = 2
 
 RADIC_MAX_M = 12
+RADIC_MAX_M_WIDE = 32
 RADIC_MAX_N = 1024
 RADIC_MAX_PRIMES = 24
 

@@ -14,7 +14,7 @@ namespace radic {
 // holds its own copy, filled by the host at first use on each device through
 // that unit's upload function.
 constexpr int kBinomRows = RADIC_MAX_N + 1;
-constexpr int kBinomCols = 16;
+constexpr int kBinomCols = 33;
 static __device__ unsigned long long g_binom[kBinomRows * kBinomCols];
 
 static inline hipError_t upload_binomial_table(const unsigned long long* host_table) {

@@ -36,6 +36,8 @@ int int_shared_lds(int m, int n, int waves, int cap);
 size_t run_bytes();
 hipError_t launch_2xn(const double* A, long long lda, long long n, int G, void* runs, void* flag,
                       radic_f64_result* out, hipStream_t s);
+hipError_t upload_binomials_wide(const unsigned long long* host_table);
+hipError_t launch_wide(const FloatJob& J, int spl, int grid, hipStream_t s);
 hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
                              unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
                              hipStream_t s);
@@ -55,7 +57,7 @@ int shared_lds(int m, int n, int prec, int waves, int cap);
 hipError_t launch_shared(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s);
 
 constexpr int kBinomRows = RADIC_MAX_N + 1;
-constexpr int kBinomCols = 16;
+constexpr int kBinomCols = 33;
 constexpr size_t kHeaderBytes = 256;
 constexpr int kMaxLds = 64 * 1024;
 constexpr unsigned long long kRankLimit = 1ull << 63;
@@ -157,6 +159,7 @@ static int ensure_device() {
     if (ue == hipSuccess) ue = upload_binomials_int(t.data());
     if (ue == hipSuccess) ue = upload_binomials_batched(t.data());
     if (ue == hipSuccess) ue = upload_binomials_shared(t.data());
+    if (ue == hipSuccess) ue = upload_binomials_wide(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
     return RADIC_OK;
@@ -259,11 +262,11 @@ static int defer_cap_for(int grid, int block) {
     return (int)c;
 }
 
-static int float_common_checks(const double* dA, int m, int n, long long lda, int prec) {
+static int float_common_checks(const double* dA, int m, int n, long long lda, int prec, int max_m = RADIC_MAX_M) {
     if (!dA || m < 1 || n < 1 || lda < n) return RADIC_EINVAL;
     if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
     if (m > n) return RADIC_OK;
-    if (m > RADIC_MAX_M || n > RADIC_MAX_N) return RADIC_ENOTSUP;
+    if (m > max_m || n > RADIC_MAX_N) return RADIC_ENOTSUP;
     return RADIC_OK;
 }
 
@@ -348,7 +351,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
                           unsigned long long count, bool whole, radic_f64_result* dOut, void* dWork,
                           size_t work_bytes, hipStream_t stream) {
     if (!dOut) return RADIC_EINVAL;
-    int rc = float_common_checks(dA, m, n, lda, prec);
+    int rc = float_common_checks(dA, m, n, lda, prec, RADIC_MAX_M_WIDE);
     if (rc != RADIC_OK) return rc;
     if ((rc = ensure_device()) != RADIC_OK) return rc;
     if (m > n) return zero_result(dOut, stream);
@@ -363,6 +366,31 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         else if (count > total - q_begin) count = total - q_begin;
     }
     if (count == 0) return zero_result(dOut, stream);
+    if (m > RADIC_MAX_M) {
+        // wide minors: a group of 32 lanes per minor, in double
+        FloatJob J{};
+        J.A = dA;
+        J.lda = lda;
+        J.m = m;
+        J.n = n;
+        J.q_begin = q_begin;
+        J.count = count;
+        unsigned char* ws = static_cast<unsigned char*>(dWork);
+        J.header = reinterpret_cast<DetHeader*>(ws);
+        J.partials = reinterpret_cast<Partial*>(ws + ws_partials());
+        const int spl = 16;
+        const unsigned long long chunks = (count + spl - 1) / spl;
+        unsigned long long g = (chunks + 3) / 4;   // 4 groups per workgroup
+        const int grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
+        hipError_t e;
+        {
+            ProfScope ps(stream);
+            e = launch_wide(J, spl, grid, stream);
+        }
+        if (e != hipSuccess) return device_error("launch of the wide-minor kernel", e);
+        e = launch_finalize_float(J.partials, grid, nullptr, 0, J.header, dOut, count, 0, stream);
+        return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
+    }
     Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
     if (!fit_lds(m, n, prec, sh)) return RADIC_ENOTSUP;
 

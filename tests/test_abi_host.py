@@ -87,7 +87,7 @@ def test_argument_validation_without_device():
     assert L.radic_det(fake, 2, 3, 2, 0, fake, fake, 1 << 20, nul) == radic.RADIC_EINVAL
     assert L.radic_det(fake, 2, 3, 3, 7, fake, fake, 1 << 20, nul) == radic.RADIC_EINVAL
     # beyond the compiled limits
-    assert L.radic_det(fake, radic.RADIC_MAX_M + 1, 40, 40, 0, fake, fake, 1 << 20, nul) == radic.RADIC_ENOTSUP
+    assert L.radic_det(fake, binding.RADIC_MAX_M_WIDE + 1, 40, 40, 0, fake, fake, 1 << 20, nul) == radic.RADIC_ENOTSUP
     assert L.radic_det(fake, 2, radic.RADIC_MAX_N + 1, radic.RADIC_MAX_N + 1, 0, fake, fake, 1 << 20,
                        nul) == radic.RADIC_ENOTSUP
     # export mode needs an output
