@@ -26,11 +26,11 @@ __host__ __device__ constexpr int align16(int b) { return (b + 15) & ~15; }
 
 template <int M> __host__ __device__ constexpr int binom_bytes(int n) { return align16(n * M * 8); }
 
-// The slice C(x, y), x < n, y < M of the table, staged in LDS as bt[x*M + y].
-template <int M>
+// The slice C(x, y), x < n, y < W of the table, staged in LDS as bt[x*W + y].
+template <int W>
 __device__ void stage_binomials(unsigned long long* bt, int n) {
-    for (int e = threadIdx.x; e < n * M; e += blockDim.x) {
-        int x = e / M, y = e - x * M;
+    for (int e = threadIdx.x; e < n * W; e += blockDim.x) {
+        int x = e / W, y = e - x * W;
         bt[e] = g_binom[x * kBinomCols + y];
     }
 }

@@ -398,7 +398,7 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
             }
             wave_lds_sync();
             double acc = 0.0;
-            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, rbase, R0, R1, p, pinv, kBatchCap,
+            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, R0, R1, p, pinv, kBatchCap,
                                 L.slot, L.incl, L.tv, lane, acc);
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);

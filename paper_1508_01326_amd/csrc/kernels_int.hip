@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
         unsigned long long r0, r1;
         prefix_block_ranks<M>(J, bt, blk, r0, r1);
         const unsigned long long rbase = first_completion_rank<M>(next, J, bt);
-        int_prefix_range<M>(cr, n, bt, M, next, pi1, rbase, r0, r1, p, pinv, J.cap, slot, incl, tv, lane, acc);
+        int_prefix_range<M>(cr, n, bt, M, next, pi1, J.n_prefix, rbase, r0, r1, p, pinv, J.cap, slot, incl, tv, lane, acc);
     }
     // fixed-order sum over the wave, then waves in order
 #pragma unroll

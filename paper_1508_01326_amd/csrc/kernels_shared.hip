@@ -35,66 +35,55 @@
 
 namespace radic {
 
-// Per-prefix record in the wave's LDS (48 bytes).
-struct SlotHdr {
+// Per-prefix records in the wave's LDS.
+struct PairHdr {      // read by phase B (16 bytes)
     double prodS;     // product of the m-2 pivots with the prefix's sign parity applied
-    int r;            // columns after the prefix: n - 1 - c_{m-3}
-    int toff;         // first projected-column slot of this prefix
     unsigned lo;      // first pair (in the prefix's pair order) inside the call's rank range
-    float ratio;      // FP32-bulk: capped pivot-ratio product of the m-2 prefix steps
-    unsigned w[4];    // packed prefix columns (FP32-bulk deferral entries)
-    int pad[2];
+    unsigned rt;      // r | toff << kRBits: r = n - 1 - c_{m-3} columns after the prefix, toff its first slot
 };
-static_assert(sizeof(SlotHdr) == 48, "slot header size");
+static_assert(sizeof(PairHdr) == 16, "pair header size");
+constexpr int kRBits = 11;
+constexpr unsigned kRMask = (1u << kRBits) - 1u;
 
+// The prefix's projection (read by the lanes that project its columns): the
+// rows m-2, m-1 of -L21 L11^{-1} and the lane's row order (4 bits per position).
+template <int P, typename T> struct alignas(16) ProjRec {
+    T z0[P];
+    T z1[P];
+    unsigned long long rel;
+};
+
+constexpr int kHdrBytes = kPrefixBlock * (int)sizeof(PairHdr);
+constexpr int kScanBytes = 2 * kPrefixBlock * 4;
+constexpr int kF32Extra = kPrefixBlock * 4 + kPrefixBlock * 16;   // capped ratios, packed prefix columns
+
+// The LDS binomial slice holds C(x, y) for y <= m (stride m + 1): the prefix
+// unranking reads y <= m-2, the rank of a prefix's first sequence y <= m.
 template <int M, bool F32> __host__ __device__ int shared_common_bytes(int n) {
-    int b = binom_bytes<M>(n) + align16(n * Layout<M>::st64 * 8);
+    int b = binom_bytes<M + 1>(n) + align16(n * Layout<M>::st64 * 8);
     if (F32) b += align16(n * Layout<M>::st32 * 4);
     return b;
 }
 
-template <int M, bool F32> __host__ __device__ int shared_wave_bytes(int n, int cap) {
-    return wave_copy_bytes<M, F32>(n) + kPrefixBlock * (int)sizeof(SlotHdr) + kPrefixBlock * 4 +
-           align16(cap * 2 * (F32 ? 4 : 8));
+// A projected-column slot is 16 bytes: (t0, t1) in double, or in float with the
+// column's two factors of the FP32-bulk conditioning test (1 / max(|t0|, |t1|)
+// and the column scale).
+constexpr int kSlotBytes = 16;
+
+template <int M, bool F32> __host__ __device__ int shared_wave_bytes(int cap) {
+    using T = typename std::conditional<F32, float, double>::type;
+    return kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0) + kPrefixBlock * (int)sizeof(ProjRec<M - 2, T>) +
+           cap * kSlotBytes;
 }
 
 template <int M, bool F32> __host__ __device__ int shared_lds_bytes(int n, int waves, int cap) {
-    return shared_common_bytes<M, F32>(n) + waves * shared_wave_bytes<M, F32>(n, cap);
-}
-
-// m x P block of the prefix columns, rows in the order of the LDS copy.
-template <int M, int P, typename T>
-__device__ __forceinline__ void gather_prefix(T (&a)[M][P], const T* base, int stride, const int (&col)[P]) {
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-        const T* src = base + col[j] * stride;
-        if constexpr (sizeof(T) == 8) {
-#pragma unroll
-            for (int i = 0; i + 1 < M; i += 2) {
-                const double2 v = *reinterpret_cast<const double2*>(src + i);
-                a[i][j] = v.x;
-                a[i + 1][j] = v.y;
-            }
-            if (M & 1) a[M - 1][j] = src[M - 1];
-        } else {
-#pragma unroll
-            for (int i = 0; i + 3 < M; i += 4) {
-                const float4 v = *reinterpret_cast<const float4*>(src + i);
-                a[i][j] = v.x;
-                a[i + 1][j] = v.y;
-                a[i + 2][j] = v.z;
-                a[i + 3][j] = v.w;
-            }
-#pragma unroll
-            for (int i = (M / 4) * 4; i < M; ++i) a[i][j] = src[i];
-        }
-    }
+    return shared_common_bytes<M, F32>(n) + waves * shared_wave_bytes<M, F32>(cap);
 }
 
 // The two values left in rows m-2, m-1 after the prefix's elimination steps,
-// for one column of the copy: with the lane's rows read in the lane's order
-// (copy row off[i] at position i), t_q = x_{m-2+q} + sum_{i<m-2} z_q[i] x_i,
-// z_q the rows m-2+q of -L21 L11^{-1}.
+// for one column: with the lane's rows read in the lane's order (row off[i] at
+// position i), t_q = x_{m-2+q} + sum_{i<m-2} z_q[i] x_i, z_q the rows m-2+q of
+// -L21 L11^{-1}.
 template <int M, int P, typename T>
 __device__ __forceinline__ void project(const T (&z0)[P], const T (&z1)[P], const int (&off)[M], const T* src,
                                         T& t0, T& t1) {
@@ -111,63 +100,70 @@ __device__ __forceinline__ void project(const T (&z0)[P], const T (&z1)[P], cons
     t1 = s1;
 }
 
-// Step K of LU with partial pivoting on the m x P prefix block, multipliers
-// stored below the diagonal (whole rows exchanged, so that P A = L U).  `rel`
-// tracks the lane's row order relative to the copy (4 bits per position);
-// exchanges made by every lane alike are also recorded in the wave's order
-// `perm` for later rounds, as in the per-minor kernel.
+// Step K of LU with partial pivoting of the m x (m-2) prefix block, column by
+// column (left-looking): column c_K is read in the lane's current row order
+// `rel` (4 bits per position), the earlier steps are applied to it with the
+// stored multipliers L, its pivot is chosen, and an exchange swaps the two rows
+// of L and of the column and is recorded in `rel`, so that later columns are read
+// already exchanged.  Every entry sees the same operations in the same order as
+// in the row-by-row (right-looking) form, P A = L U, with only L kept: U enters
+// through the pivot product.
 template <int M, int P, int K, typename T, bool CHECK>
-__device__ __forceinline__ void prefix_steps(T (&a)[M][P], double& prod, bool& neg, float& ratio, const T (&s)[P],
-                                             unsigned long long& perm, int& perm_odd, unsigned long long& rel) {
+__device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int stride, const int (&c)[P], double& prod,
+                                           bool& neg, float& ratio, unsigned long long& rel) {
     if constexpr (K < P) {
-        unsigned best = pivot_key(a[K][K], K);
+        const T* colp = src + c[K] * stride;
+        T x[M];
 #pragma unroll
-        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(a[i][K], i));
+        for (int i = 0; i < M; ++i) x[i] = colp[(int)((rel >> (4 * i)) & 15ull)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = k + 1; i < M; ++i) x[i] = fma_t(-L[i][k], x[k], x[i]);
+        }
+        unsigned best = pivot_key(x[K], K);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(x[i], i));
         const int p = pivot_row(best);
         neg ^= (p != K);
         if (__ballot(p != K)) {
-            const unsigned long long x = ((rel >> (4 * K)) ^ (rel >> (4 * p))) & 15ull;
-            rel ^= (x << (4 * K)) | (x << (4 * p));
+            const unsigned long long d = ((rel >> (4 * K)) ^ (rel >> (4 * p))) & 15ull;
+            rel ^= (d << (4 * K)) | (d << (4 * p));
         }
 #pragma unroll
         for (int i = K + 1; i < M; ++i) {
-            const bool c = (p == i);
-            const unsigned long long mask = __ballot(c);
-            if (mask) {
-                if (mask == ~0ull) {
-                    const unsigned long long x = ((perm >> (4 * K)) ^ (perm >> (4 * i))) & 15ull;
-                    perm ^= (x << (4 * K)) | (x << (4 * i));
-                    perm_odd ^= 1;
+            const bool e = (p == i);
+            if (__ballot(e)) {
+                {
+                    const T u = x[K], v = x[i];
+                    x[K] = e ? v : u;
+                    x[i] = e ? u : v;
                 }
 #pragma unroll
-                for (int j = 0; j < P; ++j) {
-                    const T x = a[K][j], y = a[i][j];
-                    a[K][j] = c ? y : x;
-                    a[i][j] = c ? x : y;
+                for (int k = 0; k < K; ++k) {
+                    const T u = L[K][k], v = L[i][k];
+                    L[K][k] = e ? v : u;
+                    L[i][k] = e ? u : v;
                 }
             }
         }
-        const T piv = a[K][K];
-        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)s[K]);
+        const T piv = x[K];
+        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)colp[M]);
         prod *= (double)piv;
         const T rp = piv == T(0) ? T(0) : recip(piv);   // a zero pivot column: every minor is 0
 #pragma unroll
-        for (int i = K + 1; i < M; ++i) {
-            const T l = a[i][K] * rp;
-            a[i][K] = l;
-#pragma unroll
-            for (int j = K + 1; j < P; ++j) a[i][j] = fma_t(-l, a[K][j], a[i][j]);
-        }
-        prefix_steps<M, P, K + 1, T, CHECK>(a, prod, neg, ratio, s, perm, perm_odd, rel);
+        for (int i = K + 1; i < M; ++i) L[i][K] = x[i] * rp;
+        left_steps<M, P, K + 1, T, CHECK>(L, src, stride, c, prod, neg, ratio, rel);
     }
 }
 
 template <int M, bool F32>
 __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     using T = typename std::conditional<F32, float, double>::type;
-    using T2 = typename std::conditional<F32, float2, double2>::type;
+    using TV = typename std::conditional<F32, float4, double2>::type;
+    static_assert(sizeof(TV) == kSlotBytes, "slot size");
     constexpr int P = M - 2;
-    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    constexpr int ST = F32 ? Layout<M>::st32 : Layout<M>::st64;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int rowexp[RADIC_MAX_M];
     __shared__ double red[4 * 16];
@@ -177,19 +173,21 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     const int waves = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
-    const int colstride = F32 ? ST32 : ST64;
 
+    constexpr int BS = M + 1;   // stride of the LDS binomial slice
     unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
-    double* cd = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
-    float* cf = reinterpret_cast<float*>(smem + binom_bytes<M>(n) + align16(n * ST64 * 8));
-    unsigned char* wr = smem + shared_common_bytes<M, F32>(n) + wave * shared_wave_bytes<M, F32>(n, J.cap);
-    T* wcopy = reinterpret_cast<T*>(wr);
-    SlotHdr* hdr = reinterpret_cast<SlotHdr*>(wr + wave_copy_bytes<M, F32>(n));
-    unsigned* incl = reinterpret_cast<unsigned*>(wr + wave_copy_bytes<M, F32>(n) + kPrefixBlock * sizeof(SlotHdr));
-    T2* tv = reinterpret_cast<T2*>(wr + wave_copy_bytes<M, F32>(n) + kPrefixBlock * sizeof(SlotHdr) +
-                                   kPrefixBlock * 4);
+    double* cd = reinterpret_cast<double*>(smem + binom_bytes<BS>(n));
+    float* cf = reinterpret_cast<float*>(smem + binom_bytes<BS>(n) + align16(n * Layout<M>::st64 * 8));
+    unsigned char* wr = smem + shared_common_bytes<M, F32>(n) + wave * shared_wave_bytes<M, F32>(J.cap);
+    PairHdr* hdr = reinterpret_cast<PairHdr*>(wr);
+    unsigned* incl = reinterpret_cast<unsigned*>(wr + kHdrBytes);   // pairs, inclusive scan over the lanes
+    unsigned* cincl = incl + kPrefixBlock;                           // columns, inclusive scan
+    float* ratios = reinterpret_cast<float*>(wr + kHdrBytes + kScanBytes);
+    uint4* wcols = reinterpret_cast<uint4*>(wr + kHdrBytes + kScanBytes + kPrefixBlock * 4);
+    ProjRec<P, T>* proj = reinterpret_cast<ProjRec<P, T>*>(wr + kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0));
+    TV* tv = reinterpret_cast<TV*>(reinterpret_cast<unsigned char*>(proj) + kPrefixBlock * sizeof(ProjRec<P, T>));
 
-    stage_binomials<M>(bt, n);
+    stage_binomials<BS>(bt, n);
     const int bad = stage_matrix<M, F32>(J, cd, cf, rowexp);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         J.header->nonfinite = bad;
@@ -199,14 +197,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
         J.header->scale_exp = se;
     }
 
-    const T* master = F32 ? reinterpret_cast<const T*>(cf) : reinterpret_cast<const T*>(cd);
+    const T* src = F32 ? reinterpret_cast<const T*>(cf) : reinterpret_cast<const T*>(cd);
     const T tau = (T)J.tau;
-    unsigned long long perm = 0;
-#pragma unroll
-    for (int r = 0; r < M; ++r) perm |= (unsigned long long)r << (4 * r);
-    int perm_odd = 0;
-    write_wave_copy<M, T>(wcopy, master, colstride, n, perm, lane, F32);
-
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nfb = 0;
     int gcount = 0;          // wave-uniform number of flagged minors (FP32-bulk)
@@ -220,23 +212,26 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
         unsigned long long next = J.p_begin + blk * kPrefixBlock;
         const unsigned long long pe = next + kPrefixBlock;
         const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
-        unsigned long long rbase = first_completion_rank<M>(next, J, bt);
         while (next < pi1 && !overflow) {
             // ---------------- the round's prefixes: lane l takes prefix next + l
             const unsigned long long pi = next + lane;
             const bool have = pi < pi1;
             int c[P];
-            unrank_strided<P>(have ? pi : next, n - 2, bt, M, c);
+            unrank_prefix<P>(have ? pi : next, n, J.n_prefix, bt, BS, c);
             const int r = n - 1 - c[P - 1];
+            // dictionary rank of the prefix's first sequence (c, c_{m-3}+1, c_{m-3}+2):
+            // the sequences after it number sum_k C(n-1-c_k, m-k)
+            unsigned long long after = bt[(r - 1) * BS + 2] + bt[(r - 2) * BS + 1];
+#pragma unroll
+            for (int k = 0; k < P; ++k) after += bt[(n - 1 - c[k]) * BS + (M - k)];
+            const unsigned long long base = J.total - 1 - after;
             // projected-column slots: lanes take prefixes while the slots last
             // (lane 0 always fits: cap >= n - m + 2 >= r)
             const unsigned rs = wave_scan_u32(have ? (unsigned)r : 0u, lane);
             const bool take = have && rs <= (unsigned)J.cap;
             const int ntake = __popcll(__ballot(take));
+            const unsigned ncols = __shfl(rs, ntake - 1, kWave);
             const unsigned cnt = take ? (unsigned)(r * (r - 1) / 2) : 0u;
-            const unsigned cincl = wave_scan_u32(cnt, lane);
-            const unsigned round_total = __shfl(cincl, kWave - 1, kWave);
-            const unsigned long long base = rbase + (cincl - cnt);
             // the prefix's pairs inside [q_begin, q_begin + count)
             unsigned lo_c = 0, hi_c = cnt;
             if (base < J.q_begin) {
@@ -253,75 +248,123 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
             const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);
 
             // ---------------- phase A: the prefix's m-2 elimination steps
-            const int perm_odd_round = perm_odd;
-            const unsigned long long perm_round = perm;
             {
-                T a[M][P];
-                gather_prefix<M, P, T>(a, wcopy, colstride, c);
-                T sc[P];
-#pragma unroll
-                for (int k = 0; k < P; ++k) sc[k] = F32 ? wcopy[c[k] * colstride + M] : T(0);
+                T L[M][P];
                 unsigned long long rel = 0;
 #pragma unroll
                 for (int q = 0; q < M; ++q) rel |= (unsigned long long)q << (4 * q);
                 double prod = 1.0;
                 bool neg = false;
                 float ratio = 1.0f;
-                prefix_steps<M, P, 0, T, F32>(a, prod, neg, ratio, sc, perm, perm_odd, rel);
+                left_steps<M, P, 0, T, F32>(L, src, ST, c, prod, neg, ratio, rel);
                 // z_t = -l_{m-2+t} L11^{-1}: rows m-2, m-1 of L^{-1} in the lane's row order
-                T z0[P], z1[P];
+                ProjRec<P, T> pr;
 #pragma unroll
                 for (int k = P - 1; k >= 0; --k) {
-                    T s0 = -a[P][k], s1 = -a[P + 1][k];
+                    T s0 = -L[P][k], s1 = -L[P + 1][k];
 #pragma unroll
                     for (int i = k + 1; i < P; ++i) {
-                        s0 = fma_t(-z0[i], a[i][k], s0);
-                        s1 = fma_t(-z1[i], a[i][k], s1);
+                        s0 = fma_t(-pr.z0[i], L[i][k], s0);
+                        s1 = fma_t(-pr.z1[i], L[i][k], s1);
                     }
-                    z0[k] = s0;
-                    z1[k] = s1;
+                    pr.z0[k] = s0;
+                    pr.z1[k] = s1;
                 }
-                // the lane's row order: position i holds copy row rel_i
-                int off[M];
-#pragma unroll
-                for (int i = 0; i < M; ++i) off[i] = (int)((rel >> (4 * i)) & 15ull);
-                // sign: row order (lane exchanges, copy order) and the prefix's share of (-1)^(r+s)
+                pr.rel = rel;
+                // sign: the lane's exchanges and the prefix's share of (-1)^(r+s)
                 int ps = M * (M + 1) / 2 + P;
 #pragma unroll
                 for (int k = 0; k < P; ++k) ps += c[k];
-                const bool sg = neg ^ (perm_odd_round != 0) ^ ((ps & 1) != 0);
-                const int toff = (int)rs - r;
+                const bool sg = neg ^ ((ps & 1) != 0);
                 if (take) {
-                    SlotHdr h;
+                    PairHdr h;
                     h.prodS = sg ? -prod : prod;
-                    h.r = r;
-                    h.toff = toff;
                     h.lo = lo_c;
-                    h.ratio = ratio;
-                    h.w[0] = h.w[1] = h.w[2] = h.w[3] = 0u;
-#pragma unroll
-                    for (int k = 0; k < P; ++k) h.w[k / 3] |= (unsigned)c[k] << (kColBits * (k % 3));
-                    h.pad[0] = h.pad[1] = 0;
+                    h.rt = (unsigned)r | ((rs - (unsigned)r) << kRBits);
                     hdr[lane] = h;
                     incl[lane] = ccincl;
-                }
-                int rmax = take ? r : 0;
+                    cincl[lane] = rs;
+                    proj[lane] = pr;
+                    if (F32) {
+                        ratios[lane] = ratio;
+                        uint4 w = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-                for (int off = kWave / 2; off > 0; off >>= 1) rmax = max(rmax, __shfl_xor(rmax, off, kWave));
-                for (int j = 0; j < rmax; ++j) {
-                    const int col = min(c[P - 1] + 1 + j, n - 1);
-                    T t0, t1;
-                    project<M, P, T>(z0, z1, off, wcopy + col * colstride, t0, t1);
-                    if (take && j < r) {
-                        T2 v;
-                        v.x = t0;
-                        v.y = t1;
-                        tv[toff + j] = v;
+                        for (int k = 0; k < P; ++k) {
+                            const unsigned v = (unsigned)c[k] << (kColBits * (k % 3));
+                            if (k / 3 == 0) w.x |= v;
+                            else if (k / 3 == 1) w.y |= v;
+                            else if (k / 3 == 2) w.z |= v;
+                            else w.w |= v;
+                        }
+                        wcols[lane] = w;
                     }
                 }
             }
             wave_lds_sync();
-            if (perm != perm_round) write_wave_copy<M, T>(wcopy, master, colstride, n, perm, lane, false);
+
+            // ---------------- projection: the round's columns split evenly over the lanes
+            {
+                const unsigned per = (ncols + kWave - 1) / kWave;
+                const unsigned g0 = (unsigned)lane * per;
+                const unsigned g1 = min(g0 + per, ncols);
+                if (g0 < g1) {
+                    // prefix owning column g0: the first s with cincl[s] > g0
+                    int s;
+                    {
+                        int l2 = 0, h2 = ntake - 1;
+                        while (l2 < h2) {
+                            const int mid = (l2 + h2) >> 1;
+                            if (cincl[mid] > g0) h2 = mid;
+                            else l2 = mid + 1;
+                        }
+                        s = l2;
+                    }
+                    unsigned send = cincl[s];
+                    unsigned sbeg = s > 0 ? cincl[s - 1] : 0u;
+                    T z0[P], z1[P];
+                    int off[M];
+                    int cb = 0;   // column of slot g: cb + g
+                    auto load = [&]() {
+                        const ProjRec<P, T> q = proj[s];
+#pragma unroll
+                        for (int i = 0; i < P; ++i) {
+                            z0[i] = q.z0[i];
+                            z1[i] = q.z1[i];
+                        }
+#pragma unroll
+                        for (int i = 0; i < M; ++i) off[i] = (int)((q.rel >> (4 * i)) & 15ull);
+                        cb = n - (int)send;   // c_{m-3} + 1 = n - r at slot sbeg
+                    };
+                    load();
+                    for (unsigned g = g0; g < g1; ++g) {
+                        if (g >= send) {
+                            ++s;
+                            sbeg = send;
+                            send = cincl[s];
+                            load();
+                        }
+                        const T* colp = src + (cb + (int)g) * ST;
+                        T t0, t1;
+                        project<M, P, T>(z0, z1, off, colp, t0, t1);
+                        // (-1)^j folded in for the j-th column after the prefix
+                        if ((g - sbeg) & 1u) {
+                            t0 = -t0;
+                            t1 = -t1;
+                        }
+                        TV v;
+                        v.x = t0;
+                        v.y = t1;
+                        if constexpr (F32) {
+                            // the column as the minor's step m-2 pivot column: its pivot max(|t|)
+                            const float pa = fmaxf(fabsf(t0), fabsf(t1));
+                            v.z = pa > 0.f ? __builtin_amdgcn_rcpf(pa) : 0.f;
+                            v.w = colp[M];   // reciprocal column scale
+                        }
+                        tv[g] = v;
+                    }
+                }
+            }
+            wave_lds_sync();
 
             // ---------------- phase B: the round's minors, split evenly over the lanes
             const unsigned chunk = (Tr + kWave - 1) / kWave;
@@ -339,37 +382,42 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                     }
                     s = active ? l2 : 0;
                 }
-                SlotHdr h = hdr[s];
+                PairHdr h = hdr[s];
+                int hr = (int)(h.rt & kRMask), toff = (int)(h.rt >> kRBits);
+                float hratio = F32 ? ratios[s] : 1.0f;
                 int ia = 0, ib = 1;
                 if (active) {
                     const unsigned excl = s > 0 ? incl[s - 1] : 0u;
-                    unrank_pair(g0 - excl + h.lo, h.r, ia, ib);
+                    unrank_pair(g0 - excl + h.lo, hr, ia, ib);
                 }
-                T2 ta = tv[h.toff + ia];
+                const unsigned kend = active ? gend - g0 : 0u;
+                TV ta = tv[toff + ia];
+                // FP32-bulk: the prefix's capped pivot ratios times the factor of
+                // the minor's step m-2 pivot, max(|t_a|) (column scale s_a)
+                float hf = 0.f;
+                if constexpr (F32) hf = hratio * fminf(fmaxf(fabsf(ta.x), fabsf(ta.y)) * ta.w, 1.f);
                 for (unsigned k = 0; k < chunk; ++k) {
-                    const bool valid = g0 + k < gend;
-                    const T2 tb = tv[h.toff + ib];
+                    const bool valid = k < kend;
+                    const TV tb = tv[toff + ib];
+                    // signed 2 x 2 determinant: (-1)^(ia+ib) is carried by the stored columns
                     const T d = fma_t(ta.x, tb.y, -(ta.y * tb.x));
-                    double term = (double)d * h.prodS;
-                    if ((ia + ib) & 1) term = -term;
-                    bool flag = false;
-                    if (F32) {
-                        // last two pivots of the minor: max(|t_a|) and det / that pivot
-                        const int ca = n - h.r + ia, cb = n - h.r + ib;
-                        const float pa = fmaxf(fabsf((float)ta.x), fabsf((float)ta.y));
-                        const float sa = cf[ca * ST32 + M], sb = cf[cb * ST32 + M];
-                        const float q = pa > 0.f ? fabsf((float)d) * __builtin_amdgcn_rcpf(pa) : 0.f;
-                        const float rt = h.ratio * __saturatef(pa * sa) * __saturatef(q * sb);
-                        flag = valid && !(rt >= (float)tau);
+                    bool keep = valid;
+                    if constexpr (F32) {
+                        // the last pivot is det / max(|t_a|), capped with the scale s_b
+                        const float rt = hf * fminf(fabsf(d) * ta.z * tb.w, 1.f);
+                        const bool flag = valid && !(rt >= (float)tau);
+                        keep = valid && !flag;
                         const unsigned long long fm = __ballot(flag);
                         if (fm) {
                             const int pos = gcount + (int)__builtin_amdgcn_mbcnt_hi(
                                                          (unsigned)(fm >> 32),
                                                          __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
                             if (flag && pos < J.defer_cap) {
-                                unsigned w[4] = {h.w[0], h.w[1], h.w[2], h.w[3]};
+                                const int ca = n - hr + ia, cbb = n - hr + ib;
+                                const uint4 pw = wcols[s];
+                                unsigned w[4] = {pw.x, pw.y, pw.z, pw.w};
                                 w[P / 3] |= (unsigned)ca << (kColBits * (P % 3));
-                                w[(P + 1) / 3] |= (unsigned)cb << (kColBits * ((P + 1) % 3));
+                                w[(P + 1) / 3] |= (unsigned)cbb << (kColBits * ((P + 1) % 3));
                                 unsigned* ent = J.fb_entries + ((size_t)gwave * J.defer_cap + pos) * 4;
                                 ent[0] = w[0];
                                 ent[1] = w[1];
@@ -378,34 +426,36 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                                 nfb += 1;
                             }
                             gcount += __popcll(fm);
-                            if (gcount > J.defer_cap) {
-                                overflow = true;
-                                break;
-                            }
                         }
                     }
-                    if (valid && !flag) {
-                        double sum, err;
-                        two_sum(hi, term, sum, err);
-                        hi = sum;
-                        lo += err;
-                        ab += fabs(term);
-                    }
+                    // a minor outside the lane's share, or queued, adds an exact 0
+                    const double term = keep ? (double)d * h.prodS : 0.0;
+                    double sum, err;
+                    two_sum(hi, term, sum, err);
+                    hi = sum;
+                    lo += err;
+                    ab += fabs(term);
                     // next pair; past the prefix's last pair, the next prefix
-                    if (++ib >= h.r) {
+                    if (++ib >= hr) {
                         ++ia;
                         ib = ia + 1;
-                        if (ib >= h.r) {
+                        if (ib >= hr) {
                             s = min(s + 1, ntake - 1);
                             h = hdr[s];
+                            hr = (int)(h.rt & kRMask);
+                            toff = (int)(h.rt >> kRBits);
+                            if (F32) hratio = ratios[s];
                             ia = 0;
                             ib = 1;
                         }
-                        ta = tv[h.toff + ia];
+                        ta = tv[toff + ia];
+                        if constexpr (F32) hf = hratio * fminf(fmaxf(fabsf(ta.x), fabsf(ta.y)) * ta.w, 1.f);
                     }
                 }
             }
-            rbase += round_total;
+            // a full segment: the workgroup is redone in double by the
+            // refactorisation kernel, so the rest is not needed
+            if (F32 && gcount > J.defer_cap) overflow = true;
             next += (unsigned long long)ntake;
             wave_lds_sync();
         }
@@ -448,23 +498,31 @@ int shared_lds(int m, int n, int prec, int waves, int cap) {
     }
 }
 
+template <int M, bool F32>
+static hipError_t launch_shared_m(const FloatJob& J, int grid, int block, int lds, hipStream_t s) {
+    // beyond 64 KiB of dynamic LDS the kernel has to be allowed it first
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_radic_shared<M, F32>),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    (void)hipGetLastError();
+    hipLaunchKernelGGL((k_radic_shared<M, F32>), dim3(grid), dim3(block), lds, s, J);
+    return hipGetLastError();
+}
+
 hipError_t launch_shared(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s) {
     const int lds = shared_lds(m, J.n, prec, block / kWave, J.cap);
-    (void)hipGetLastError();
     switch (m) {
-#define RADIC_CASE(MM)                                                                                  \
-    case MM:                                                                                            \
-        if (prec == RADIC_FP32_BULK)                                                                    \
-            hipLaunchKernelGGL((k_radic_shared<MM, true>), dim3(grid), dim3(block), lds, s, J);         \
-        else                                                                                            \
-            hipLaunchKernelGGL((k_radic_shared<MM, false>), dim3(grid), dim3(block), lds, s, J);        \
-        break;
+#define RADIC_CASE(MM)                                                                              \
+    case MM:                                                                                        \
+        return prec == RADIC_FP32_BULK ? launch_shared_m<MM, true>(J, grid, block, lds, s)          \
+                                       : launch_shared_m<MM, false>(J, grid, block, lds, s);
         RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6) RADIC_CASE(7) RADIC_CASE(8)
         RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
 #undef RADIC_CASE
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace radic

@@ -14,6 +14,44 @@ namespace radic {
 
 constexpr int kPrefixBlock = 64;
 
+// Prefix number pi to its columns c_0 < ... < c_{m-3}, through the
+// combinatorial number system: with x_k = n - 3 - c_k (strictly decreasing),
+// the prefixes after pi in dictionary order number
+// N = n_prefix - 1 - pi = sum_k C(x_k, m-2-k), so each x_k is the largest x below
+// x_{k-1} with C(x, m-2-k) <= what is left of N.  A binary search over the LDS
+// binomial slice (bt[x*stride + y] = C(x, y)) finds the leading digits; the last
+// two have closed forms.
+template <int P>
+__device__ __forceinline__ void unrank_prefix(unsigned long long pi, int n, unsigned long long n_prefix,
+                                              const unsigned long long* bt, int stride, int (&c)[P]) {
+    unsigned long long N = n_prefix - 1 - pi;
+    int hi = n - 3;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const int j = P - k;
+        int x;
+        if (j == 1) {
+            x = (int)N;
+        } else if (j == 2) {
+            x = (int)((1.0 + sqrt(1.0 + 8.0 * (double)N)) * 0.5);
+            if ((unsigned long long)x * (unsigned long long)(x - 1) / 2 > N) --x;
+            if ((unsigned long long)(x + 1) * (unsigned long long)x / 2 <= N) ++x;
+            N -= (unsigned long long)x * (unsigned long long)(x - 1) / 2;
+        } else {
+            int lo = j - 1, h = hi;
+            while (lo < h) {
+                const int mid = (lo + h + 1) >> 1;
+                if (bt[mid * stride + j] <= N) lo = mid;
+                else h = mid - 1;
+            }
+            x = lo;
+            N -= bt[x * stride + j];
+        }
+        c[k] = n - 3 - x;
+        hi = x - 1;
+    }
+}
+
 // Dictionary rank of the first sequence with prefix number pi, (c, c_{m-3}+1,
 // c_{m-3}+2); J.total when pi is past the last prefix.  Reads the LDS binomial
 // slice bt[x*M + y] = C(x, y).
@@ -24,7 +62,7 @@ __device__ unsigned long long first_completion_rank(unsigned long long pi, const
     if (pi >= J.n_prefix) return J.total;
     const int n = J.n;
     int c[P];
-    unrank_strided<P>(pi, n - 2, bt, stride, c);
+    unrank_prefix<P>(pi, n, J.n_prefix, bt, stride, c);
     int full[M];
 #pragma unroll
     for (int k = 0; k < P; ++k) full[k] = c[k];

@@ -60,6 +60,7 @@ constexpr int kBinomRows = RADIC_MAX_N + 1;
 constexpr int kBinomCols = 33;
 constexpr size_t kHeaderBytes = 256;
 constexpr int kMaxLds = 64 * 1024;
+constexpr int kSharedLds = 79 * 1024;   // dynamic LDS per prefix-shared workgroup (two per 160 KiB compute unit)
 constexpr unsigned long long kRankLimit = 1ull << 63;
 
 // ---------------------------------------------------------------- binomials
@@ -135,7 +136,9 @@ static std::mutex g_mu;
 static bool g_dev_ready[64];
 static int g_dev_prime_version[64];
 
-static int ensure_device() {
+static int g_dev_lds[64];   // dynamic LDS a workgroup may use, per device
+
+static int ensure_device(int* lds_limit = nullptr) {
     int dev = 0;
     hipError_t ge = hipGetDevice(&dev);
     if (ge != hipSuccess) return device_error("hipGetDevice", ge);
@@ -147,7 +150,15 @@ static int ensure_device() {
         if (pe != hipSuccess) return device_error("upload of the prime set", pe);
         g_dev_prime_version[dev] = g_prime_version;
     }
-    if (g_dev_ready[dev]) return RADIC_OK;
+    if (g_dev_ready[dev]) {
+        if (lds_limit) *lds_limit = g_dev_lds[dev];
+        return RADIC_OK;
+    }
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || lds < kMaxLds)
+        lds = kMaxLds;
+    g_dev_lds[dev] = lds;
+    if (lds_limit) *lds_limit = lds;
     std::vector<unsigned long long> t((size_t)kBinomRows * kBinomCols, 0);
     for (int x = 0; x < kBinomRows; ++x)
         for (int y = 0; y < kBinomCols; ++y) {
@@ -340,11 +351,16 @@ static bool shared_eligible(int m, int prec) {
     return m >= 3 && (prec == RADIC_FP32_BULK ? m <= 12 : m <= 10);
 }
 
-// Projected-column slots per wave: enough for one prefix of the widest kind.
-static int shared_cap(int m, int n, int prec) {
+// Projected-column slots per wave: what the workgroup LDS budget leaves after
+// the per-wave records, at least one prefix of the widest kind (n - m + 2
+// columns) and at most what a block of 64 prefixes can fill.
+static int shared_cap(int m, int n, int prec, int waves) {
     const int need = n - m + 2;
-    const int dflt = prec == RADIC_FP32_BULK ? 512 : 256;
-    return need > dflt ? need : dflt;
+    const int slot = 16;   // bytes per projected-column slot
+    const int fixed = shared_lds(m, n, prec, waves, 0);
+    int cap = (kSharedLds - fixed) / (waves * slot);
+    if (cap > 64 * need) cap = 64 * need;
+    return cap > need ? cap : need;
 }
 
 static int det_range_impl(const double* dA, int m, int n, long long lda, int prec, unsigned long long q_begin,
@@ -353,7 +369,8 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     if (!dOut) return RADIC_EINVAL;
     int rc = float_common_checks(dA, m, n, lda, prec, RADIC_MAX_M_WIDE);
     if (rc != RADIC_OK) return rc;
-    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    int lds_limit = kMaxLds;
+    if ((rc = ensure_device(&lds_limit)) != RADIC_OK) return rc;
     if (m > n) return zero_result(dOut, stream);
     unsigned long long total = 0;
     if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
@@ -418,13 +435,16 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     bool shared = shared_eligible(m, prec);
     if (shared) {
         J.mapping = 1;
-        J.cap = shared_cap(m, n, prec);
         host_binomial(n - 2, m - 2, &J.n_prefix);
         J.p_begin = host_prefix_index(m, n, q_begin);
         J.p_end = host_prefix_index(m, n, q_begin + count - 1) + 1;
         int block = sh.block;
-        while (block > kWave && shared_lds(m, n, prec, block / kWave, J.cap) > kMaxLds) block -= kWave;
-        if (shared_lds(m, n, prec, block / kWave, J.cap) > kMaxLds) {
+        J.cap = shared_cap(m, n, prec, block / kWave);
+        while (block > kWave && shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
+            block -= kWave;
+            J.cap = shared_cap(m, n, prec, block / kWave);
+        }
+        if (shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
             shared = false;
             J.mapping = 0;
         } else {

@@ -92,11 +92,13 @@ __device__ __forceinline__ void int_prefix_steps(double (&a)[M][P], double (&u)[
 // mod p are staged column-major in cr (stride IntLayout<M>::st), summed into
 // this lane's `acc`.  `next` is the prefix holding R0 and `rbase` the rank of its
 // first sequence; prefixes [next, pi1) are visited in rounds of up to 64 (one
-// per lane; while their later columns fit the cap projected-column slots).
+// per lane; while their later columns fit the cap projected-column slots);
+// n_prefix = C(n-2, m-2) numbers all prefixes.
 // bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform control flow throughout.
 template <int M>
 __device__ void int_prefix_range(const double* cr, int n, const unsigned long long* bt, int bstride,
-                                 unsigned long long next, unsigned long long pi1, unsigned long long rbase,
+                                 unsigned long long next, unsigned long long pi1, unsigned long long n_prefix,
+                                 unsigned long long rbase,
                                  unsigned long long R0, unsigned long long R1, double p, double pinv, int cap,
                                  IntSlot* slot, unsigned* incl, double2* tv, int lane, double& acc) {
     constexpr int P = M - 2;
@@ -107,7 +109,7 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
         const unsigned long long pi = next + lane;
         const bool inb = pi < pi1;
         int c[P];
-        unrank_strided<P>(inb ? pi : next, n - 2, bt, bstride, c);
+        unrank_prefix<P>(inb ? pi : next, n, n_prefix, bt, bstride, c);
         const int r = n - 1 - c[P - 1];
         const unsigned cfull = inb ? (unsigned)(r * (r - 1) / 2) : 0u;
         const unsigned cscan = wave_scan_u32(cfull, lane);
