@@ -475,9 +475,13 @@ static hipError_t launch_dispatch(int m, const FloatJob& J, int grid, int block,
     }
 }
 
-// Float workgroups per refactorisation workgroup: as many as keep the
-// segments of one refactorisation workgroup within one wave's scan (64).
-int refactor_group(int block) { return kWave / (block / kWave); }
+// Float workgroups per refactorisation workgroup: at most four (more workgroups
+// spread the few flagged minors over more of the chip), and no more than keep
+// the segments of one refactorisation workgroup within one wave's scan (64).
+int refactor_group(int block) {
+    const int r = kWave / (block / kWave);
+    return r < 4 ? r : 4;
+}
 
 int refactor_grid(int grid, int block) {
     const int R = refactor_group(block);

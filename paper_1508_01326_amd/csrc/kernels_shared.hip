@@ -45,35 +45,35 @@ static_assert(sizeof(PairHdr) == 16, "pair header size");
 constexpr int kRBits = 11;
 constexpr unsigned kRMask = (1u << kRBits) - 1u;
 
-// The prefix's projection (read by the lanes that project its columns): the
-// rows m-2, m-1 of -L21 L11^{-1} and the lane's row order (4 bits per position).
-template <int P, typename T> struct alignas(16) ProjRec {
-    T z0[P];
-    T z1[P];
-    unsigned long long rel;
-};
-
 constexpr int kHdrBytes = kPrefixBlock * (int)sizeof(PairHdr);
 constexpr int kScanBytes = 2 * kPrefixBlock * 4;
 constexpr int kF32Extra = kPrefixBlock * 4 + kPrefixBlock * 16;   // capped ratios, packed prefix columns
 
+// Column strides of the workgroup's matrix copies: odd (in 4- or 8-byte words),
+// so that lanes reading consecutive columns, or runs of an odd number of
+// columns apart, hit different LDS banks.  The float copy keeps the column's
+// reciprocal scale in slot m.
+template <int M> struct SharedLayout {
+    static constexpr int s64 = M | 1;
+    static constexpr int s32 = (M + 1) | 1;
+};
+
 // The LDS binomial slice holds C(x, y) for y <= m (stride m + 1): the prefix
 // unranking reads y <= m-2, the rank of a prefix's first sequence y <= m.
 template <int M, bool F32> __host__ __device__ int shared_common_bytes(int n) {
-    int b = binom_bytes<M + 1>(n) + align16(n * Layout<M>::st64 * 8);
-    if (F32) b += align16(n * Layout<M>::st32 * 4);
+    int b = binom_bytes<M + 1>(n) + align16(n * SharedLayout<M>::s64 * 8);
+    if (F32) b += align16(n * SharedLayout<M>::s32 * 4);
     return b;
 }
 
 // A projected-column slot is 16 bytes: (t0, t1) in double, or in float with the
-// column's two factors of the FP32-bulk conditioning test (1 / max(|t0|, |t1|)
-// and the column scale).
+// column's pivot max(|t0|, |t1|) and reciprocal scale for the FP32-bulk
+// conditioning test.
 constexpr int kSlotBytes = 16;
 
 template <int M, bool F32> __host__ __device__ int shared_wave_bytes(int cap) {
     using T = typename std::conditional<F32, float, double>::type;
-    return kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0) + kPrefixBlock * (int)sizeof(ProjRec<M - 2, T>) +
-           cap * kSlotBytes;
+    return kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0) + cap * kSlotBytes;
 }
 
 template <int M, bool F32> __host__ __device__ int shared_lds_bytes(int n, int waves, int cap) {
@@ -163,7 +163,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     using TV = typename std::conditional<F32, float4, double2>::type;
     static_assert(sizeof(TV) == kSlotBytes, "slot size");
     constexpr int P = M - 2;
-    constexpr int ST = F32 ? Layout<M>::st32 : Layout<M>::st64;
+    constexpr int S64 = SharedLayout<M>::s64, S32 = SharedLayout<M>::s32;
+    constexpr int ST = F32 ? S32 : S64;
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int rowexp[RADIC_MAX_M];
     __shared__ double red[4 * 16];
@@ -177,18 +178,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     constexpr int BS = M + 1;   // stride of the LDS binomial slice
     unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
     double* cd = reinterpret_cast<double*>(smem + binom_bytes<BS>(n));
-    float* cf = reinterpret_cast<float*>(smem + binom_bytes<BS>(n) + align16(n * Layout<M>::st64 * 8));
+    float* cf = reinterpret_cast<float*>(smem + binom_bytes<BS>(n) + align16(n * S64 * 8));
     unsigned char* wr = smem + shared_common_bytes<M, F32>(n) + wave * shared_wave_bytes<M, F32>(J.cap);
     PairHdr* hdr = reinterpret_cast<PairHdr*>(wr);
     unsigned* incl = reinterpret_cast<unsigned*>(wr + kHdrBytes);   // pairs, inclusive scan over the lanes
     unsigned* cincl = incl + kPrefixBlock;                           // columns, inclusive scan
     float* ratios = reinterpret_cast<float*>(wr + kHdrBytes + kScanBytes);
     uint4* wcols = reinterpret_cast<uint4*>(wr + kHdrBytes + kScanBytes + kPrefixBlock * 4);
-    ProjRec<P, T>* proj = reinterpret_cast<ProjRec<P, T>*>(wr + kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0));
-    TV* tv = reinterpret_cast<TV*>(reinterpret_cast<unsigned char*>(proj) + kPrefixBlock * sizeof(ProjRec<P, T>));
+    TV* tv = reinterpret_cast<TV*>(wr + kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0));
 
     stage_binomials<BS>(bt, n);
-    const int bad = stage_matrix<M, F32>(J, cd, cf, rowexp);
+    const int bad = stage_matrix<M, F32, F32, S64, S32>(J, cd, cf, rowexp);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         J.header->nonfinite = bad;
         int se = 0;
@@ -248,6 +248,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
             const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);
 
             // ---------------- phase A: the prefix's m-2 elimination steps
+            T pz0[P], pz1[P];          // the prefix's projection rows, kept for the exchange below
+            unsigned long long prel;   // and its row order
             {
                 T L[M][P];
                 unsigned long long rel = 0;
@@ -258,19 +260,18 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                 float ratio = 1.0f;
                 left_steps<M, P, 0, T, F32>(L, src, ST, c, prod, neg, ratio, rel);
                 // z_t = -l_{m-2+t} L11^{-1}: rows m-2, m-1 of L^{-1} in the lane's row order
-                ProjRec<P, T> pr;
 #pragma unroll
                 for (int k = P - 1; k >= 0; --k) {
                     T s0 = -L[P][k], s1 = -L[P + 1][k];
 #pragma unroll
                     for (int i = k + 1; i < P; ++i) {
-                        s0 = fma_t(-pr.z0[i], L[i][k], s0);
-                        s1 = fma_t(-pr.z1[i], L[i][k], s1);
+                        s0 = fma_t(-pz0[i], L[i][k], s0);
+                        s1 = fma_t(-pz1[i], L[i][k], s1);
                     }
-                    pr.z0[k] = s0;
-                    pr.z1[k] = s1;
+                    pz0[k] = s0;
+                    pz1[k] = s1;
                 }
-                pr.rel = rel;
+                prel = rel;
                 // sign: the lane's exchanges and the prefix's share of (-1)^(r+s)
                 int ps = M * (M + 1) / 2 + P;
 #pragma unroll
@@ -284,7 +285,6 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                     hdr[lane] = h;
                     incl[lane] = ccincl;
                     cincl[lane] = rs;
-                    proj[lane] = pr;
                     if (F32) {
                         ratios[lane] = ratio;
                         uint4 w = make_uint4(0u, 0u, 0u, 0u);
@@ -304,46 +304,54 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
 
             // ---------------- projection: the round's columns split evenly over the lanes
             {
-                const unsigned per = (ncols + kWave - 1) / kWave;
+                // runs of an odd number of columns start the lanes on different LDS banks
+                const unsigned per = ((ncols + kWave - 1) / kWave) | 1u;
                 const unsigned g0 = (unsigned)lane * per;
                 const unsigned g1 = min(g0 + per, ncols);
-                if (g0 < g1) {
-                    // prefix owning column g0: the first s with cincl[s] > g0
-                    int s;
-                    {
-                        int l2 = 0, h2 = ntake - 1;
-                        while (l2 < h2) {
-                            const int mid = (l2 + h2) >> 1;
-                            if (cincl[mid] > g0) h2 = mid;
-                            else l2 = mid + 1;
-                        }
-                        s = l2;
+                // prefix owning column g0: the first s with cincl[s] > g0 (the last
+                // taken prefix for a lane without columns)
+                int s = ntake - 1;
+                if (g0 < ncols) {
+                    int l2 = 0, h2 = ntake - 1;
+                    while (l2 < h2) {
+                        const int mid = (l2 + h2) >> 1;
+                        if (cincl[mid] > g0) h2 = mid;
+                        else l2 = mid + 1;
                     }
-                    unsigned send = cincl[s];
-                    unsigned sbeg = s > 0 ? cincl[s - 1] : 0u;
-                    T z0[P], z1[P];
-                    int off[M];
-                    int cb = 0;   // column of slot g: cb + g
-                    auto load = [&]() {
-                        const ProjRec<P, T> q = proj[s];
+                    s = l2;
+                }
+                unsigned send = cincl[s];
+                unsigned sbeg = s > 0 ? cincl[s - 1] : 0u;
+                T z0[P], z1[P];
+                int off[M];
+                // the projection rows of prefix s, from its owner lane (every lane
+                // takes part in the exchange)
+                auto fetch = [&]() {
 #pragma unroll
-                        for (int i = 0; i < P; ++i) {
-                            z0[i] = q.z0[i];
-                            z1[i] = q.z1[i];
-                        }
+                    for (int i = 0; i < P; ++i) {
+                        z0[i] = __shfl(pz0[i], s, kWave);
+                        z1[i] = __shfl(pz1[i], s, kWave);
+                    }
+                    const unsigned long long rl = __shfl(prel, s, kWave);
 #pragma unroll
-                        for (int i = 0; i < M; ++i) off[i] = (int)((q.rel >> (4 * i)) & 15ull);
-                        cb = n - (int)send;   // c_{m-3} + 1 = n - r at slot sbeg
-                    };
-                    load();
-                    for (unsigned g = g0; g < g1; ++g) {
-                        if (g >= send) {
+                    for (int i = 0; i < M; ++i) off[i] = (int)((rl >> (4 * i)) & 15ull);
+                };
+                fetch();
+                for (unsigned it = 0; it < per; ++it) {
+                    const unsigned g = g0 + it;
+                    const bool act = g < g1;
+                    const bool cross = act && g >= send;
+                    if (__ballot(cross)) {
+                        if (cross) {
                             ++s;
                             sbeg = send;
                             send = cincl[s];
-                            load();
                         }
-                        const T* colp = src + (cb + (int)g) * ST;
+                        fetch();
+                    }
+                    if (act) {
+                        // slot g holds column c_{m-3} + 1 + (g - sbeg) = n - send + g
+                        const T* colp = src + (n - (int)send + (int)g) * ST;
                         T t0, t1;
                         project<M, P, T>(z0, z1, off, colp, t0, t1);
                         // (-1)^j folded in for the j-th column after the prefix
@@ -355,10 +363,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                         v.x = t0;
                         v.y = t1;
                         if constexpr (F32) {
-                            // the column as the minor's step m-2 pivot column: its pivot max(|t|)
-                            const float pa = fmaxf(fabsf(t0), fabsf(t1));
-                            v.z = pa > 0.f ? __builtin_amdgcn_rcpf(pa) : 0.f;
-                            v.w = colp[M];   // reciprocal column scale
+                            v.z = fmaxf(fabsf(t0), fabsf(t1));   // as the minor's step m-2 pivot column
+                            v.w = colp[M];                       // reciprocal column scale
                         }
                         tv[g] = v;
                     }
@@ -392,10 +398,20 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                 }
                 const unsigned kend = active ? gend - g0 : 0u;
                 TV ta = tv[toff + ia];
-                // FP32-bulk: the prefix's capped pivot ratios times the factor of
-                // the minor's step m-2 pivot, max(|t_a|) (column scale s_a)
-                float hf = 0.f;
-                if constexpr (F32) hf = hratio * fminf(fmaxf(fabsf(ta.x), fabsf(ta.y)) * ta.w, 1.f);
+                // FP32-bulk: the minor's capped ratio product is
+                // rho = h * min(|det| s_b / p_a, 1), h = (prefix ratios) * min(p_a s_a, 1)
+                // with p_a = max(|t_a|), the step m-2 pivot; rho < tau exactly when
+                // h < tau or |det| s_b < tau p_a / h, a threshold fixed per column a
+                float thr = 0.f;
+                auto threshold = [&]() {
+                    if constexpr (F32) {
+                        const float h2 = hratio * fminf(ta.z * ta.w, 1.f);
+                        thr = !(h2 >= (float)tau)
+                                  ? __builtin_inff()
+                                  : ((float)tau > 0.f ? (float)tau * ta.z * __builtin_amdgcn_rcpf(h2) : 0.f);
+                    }
+                };
+                if constexpr (F32) threshold();
                 for (unsigned k = 0; k < chunk; ++k) {
                     const bool valid = k < kend;
                     const TV tb = tv[toff + ib];
@@ -403,9 +419,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                     const T d = fma_t(ta.x, tb.y, -(ta.y * tb.x));
                     bool keep = valid;
                     if constexpr (F32) {
-                        // the last pivot is det / max(|t_a|), capped with the scale s_b
-                        const float rt = hf * fminf(fabsf(d) * ta.z * tb.w, 1.f);
-                        const bool flag = valid && !(rt >= (float)tau);
+                        const bool flag = valid && (fabsf(d) * tb.w < thr);
                         keep = valid && !flag;
                         const unsigned long long fm = __ballot(flag);
                         if (fm) {
@@ -449,7 +463,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                             ib = 1;
                         }
                         ta = tv[toff + ia];
-                        if constexpr (F32) hf = hratio * fminf(fmaxf(fabsf(ta.x), fabsf(ta.y)) * ta.w, 1.f);
+                        if constexpr (F32) threshold();
                     }
                 }
             }

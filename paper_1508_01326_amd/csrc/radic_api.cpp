@@ -60,7 +60,7 @@ constexpr int kBinomRows = RADIC_MAX_N + 1;
 constexpr int kBinomCols = 33;
 constexpr size_t kHeaderBytes = 256;
 constexpr int kMaxLds = 64 * 1024;
-constexpr int kSharedLds = 79 * 1024;   // dynamic LDS per prefix-shared workgroup (two per 160 KiB compute unit)
+constexpr int kSharedLds = 50 * 1024;   // dynamic LDS per prefix-shared workgroup (three per 160 KiB compute unit)
 constexpr unsigned long long kRankLimit = 1ull << 63;
 
 // ---------------------------------------------------------------- binomials
@@ -354,11 +354,12 @@ static bool shared_eligible(int m, int prec) {
 // Projected-column slots per wave: what the workgroup LDS budget leaves after
 // the per-wave records, at least one prefix of the widest kind (n - m + 2
 // columns) and at most what a block of 64 prefixes can fill.
-static int shared_cap(int m, int n, int prec, int waves) {
+static int shared_cap(int m, int n, int prec, int waves, int lds_limit) {
     const int need = n - m + 2;
     const int slot = 16;   // bytes per projected-column slot
     const int fixed = shared_lds(m, n, prec, waves, 0);
-    int cap = (kSharedLds - fixed) / (waves * slot);
+    const int budget = kSharedLds < lds_limit ? kSharedLds : lds_limit;
+    int cap = (budget - fixed) / (waves * slot);
     if (cap > 64 * need) cap = 64 * need;
     return cap > need ? cap : need;
 }
@@ -439,10 +440,10 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         J.p_begin = host_prefix_index(m, n, q_begin);
         J.p_end = host_prefix_index(m, n, q_begin + count - 1) + 1;
         int block = sh.block;
-        J.cap = shared_cap(m, n, prec, block / kWave);
+        J.cap = shared_cap(m, n, prec, block / kWave, lds_limit);
         while (block > kWave && shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
             block -= kWave;
-            J.cap = shared_cap(m, n, prec, block / kWave);
+            J.cap = shared_cap(m, n, prec, block / kWave, lds_limit);
         }
         if (shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
             shared = false;

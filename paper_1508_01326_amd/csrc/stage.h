@@ -33,10 +33,11 @@ __device__ void write_wave_copy(T* dst, const T* master, int stride, int n, unsi
 // F32: rows scaled by 2^-e_i, e_i the exponent of the row maximum
 // (max_j |a_ij| = f 2^e_i with f in [0.5, 1)); WITH_F32: also write the float
 // copy and its reciprocal column scales.  Each wave loads whole rows (coalesced)
-// and takes the row maximum by a butterfly.
-template <int M, bool F32, bool WITH_F32 = F32>
+// and takes the row maximum by a butterfly.  Column strides ST64 (doubles) and
+// ST32 (floats, the scale in slot M).
+template <int M, bool F32, bool WITH_F32 = F32, int ST64 = Layout<M>::st64, int ST32 = Layout<M>::st32>
 __device__ int stage_matrix(const FloatJob& J, double* cd, float* cf, int* rowexp) {
-    constexpr int ST64 = Layout<M>::st64, ST32 = Layout<M>::st32;
+    static_assert(ST64 >= M && ST32 >= M + 1, "column strides");
     const int n = J.n;
     const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     int bad = 0;
