@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared"],
+    ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared", "group_shared"],
                     help="enumeration used by the library (default: auto, prefix-shared where supported)")
     ap.add_argument("--other", action="store_true",
                     help="also time the exact-integer workload (6x40 int32) and the batched workload "

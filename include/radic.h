@@ -280,9 +280,17 @@ int radic_set_fallback_tau(double tau);
  *                             minor then costs its last two elimination steps.
  *                             Used for 3 <= m <= 10 (FP64) or m <= 12
  *                             (FP32_BULK); other shapes fall back to per-minor.
- * Both give every minor's determinant (the terms of eq. (1)) individually; they
- * differ in rounding only.  radic_det_subsets always uses per-minor.  The same
- * switch applies to radic_det_int_exact (prefix-shared for 3 <= m <= 10: the
+ *  RADIC_ENUM_GROUP_SHARED    the minors sharing their first m-3 columns share
+ *                             those m-3 steps; each minor then costs the
+ *                             determinant of its last 3 x 3 block, a dot
+ *                             product with a cross product formed once per
+ *                             pair of its last three columns.  Used for
+ *                             4 <= m <= 10 (FP64) or m <= 12 (FP32_BULK); m = 3
+ *                             falls back to prefix-shared.
+ * RADIC_ENUM_AUTO takes prefix-shared where supported.  All give every minor's
+ * determinant (the terms of eq. (1)) individually; they differ in rounding only.
+ * radic_det_subsets always uses per-minor.  The same switch applies to
+ * radic_det_int_exact (any shared mode: prefix-shared for 3 <= m <= 10: the
  * minors of a prefix share its fraction-free elimination steps modulo p; the
  * result is the same exact integer either way).
  * Returns RADIC_EINVAL for an unknown mode.
@@ -290,6 +298,7 @@ int radic_set_fallback_tau(double tau);
 #define RADIC_ENUM_AUTO 0
 #define RADIC_ENUM_PER_MINOR 1
 #define RADIC_ENUM_PREFIX_SHARED 2
+#define RADIC_ENUM_GROUP_SHARED 3
 int radic_set_enumeration(int mode);
 
 /*

@@ -33,6 +33,7 @@ RADIC_WS_BATCHED = 2
 RADIC_ENUM_AUTO = 0
 RADIC_ENUM_PER_MINOR = 1
 RADIC_ENUM_PREFIX_SHARED = 2
+RADIC_ENUM_GROUP_SHARED = 3
 
 RADIC_MAX_M = 12
 RADIC_MAX_M_WIDE = 32
@@ -297,12 +298,12 @@ def set_fallback_tau(tau):
 
 
 ENUMERATIONS = {"auto": RADIC_ENUM_AUTO, "per_minor": RADIC_ENUM_PER_MINOR,
-                "prefix_shared": RADIC_ENUM_PREFIX_SHARED}
+                "prefix_shared": RADIC_ENUM_PREFIX_SHARED, "group_shared": RADIC_ENUM_GROUP_SHARED}
 
 
 def set_enumeration(mode="auto"):
-    """Enumeration used by radic_det / radic_det_range: "auto", "per_minor" or
-    "prefix_shared" (or the RADIC_ENUM_* value)."""
+    """Enumeration used by radic_det / radic_det_range: "auto", "per_minor",
+    "prefix_shared" or "group_shared" (or the RADIC_ENUM_* value)."""
     code = ENUMERATIONS[mode] if isinstance(mode, str) else int(mode)
     _check(lib().radic_set_enumeration(code), "radic_set_enumeration")
 

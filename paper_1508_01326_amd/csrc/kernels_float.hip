@@ -328,13 +328,25 @@ __global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J, int
             const unsigned long long nw = (unsigned long long)G * waves;
             if (J.mapping == 0) {
                 redo_wave_f64<M>(J, bt, cd, gw, nw, lane, hi, lo, ab, nfb);
-            } else if constexpr (M >= 3) {
-                // the prefix blocks this wave of the float launch was given
-                const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
-                for (unsigned long long blk = gw; blk < nblk; blk += nw) {
-                    unsigned long long r0, r1;
-                    prefix_block_ranks<M>(J, bt, blk, r0, r1);
-                    redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+            } else if (J.mapping == 1) {
+                if constexpr (M >= 3) {
+                    // the blocks of m-2 column prefixes this wave of the float launch was given
+                    const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+                    for (unsigned long long blk = gw; blk < nblk; blk += nw) {
+                        unsigned long long r0, r1;
+                        prefix_block_ranks<M>(J, bt, blk, r0, r1);
+                        redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                    }
+                }
+            } else {
+                if constexpr (M >= 4) {
+                    // the blocks of m-3 column prefixes
+                    const unsigned long long nblk = (J.p_end - J.p_begin + kGroupBlock - 1) / kGroupBlock;
+                    for (unsigned long long blk = gw; blk < nblk; blk += nw) {
+                        unsigned long long r0, r1;
+                        prefix_block_ranks<M, FloatJob, 3, kGroupBlock>(J, bt, blk, r0, r1);
+                        redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                    }
                 }
             }
             if (threadIdx.x == 0) J.partials[fb0 + b] = Partial{0.0, 0.0, 0.0, 0ull};

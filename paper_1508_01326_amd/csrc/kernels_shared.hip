@@ -9,12 +9,13 @@
 //
 // A wave takes a block of 64 consecutive prefixes and works in rounds:
 //  A. Each lane takes one prefix and factors the m x (m-2) block of its columns
-//     by LU with partial pivoting in registers (the first m-2 steps of every
-//     minor with that prefix).  From the multipliers it forms the two rows of
-//     the projection onto the two rows left after those steps, W = rows m-2 and
-//     m-1 of L^{-1} P.  It writes W x_c for every later column c (2 values per
-//     column, the column read in the lane's row order) to its slot in the
-//     wave's LDS, with the signed product of the m-2 pivots.
+//     by LU with partial pivoting in registers, column by column (the first m-2
+//     steps of every minor with that prefix).  From the multipliers it forms
+//     the two rows of the projection onto the rows left after those steps,
+//     W = rows m-2 and m-1 of L^{-1} P, with the signed product of the pivots.
+//  P. The round's later columns (r per prefix) are split evenly over the lanes;
+//     a lane fetches W of the prefix owning its column from the owner lane by a
+//     cross-lane exchange and writes (-1)^j W x_c to the wave's LDS.
 //  B. The wave's minors (the column pairs (a, b) after each prefix, in
 //     dictionary order) are split evenly over the 64 lanes.  Each minor is
 //     det(A_J) = (signed pivot product) * det([W x_a, W x_b]).  Its last two
@@ -30,41 +31,9 @@
 // refactorisation kernel exactly as in the per-minor kernel.
 #include <type_traits>
 
-#include "prefix.h"
-#include "stage.h"
+#include "shared_lu.h"
 
 namespace radic {
-
-// Per-prefix records in the wave's LDS.
-struct PairHdr {      // read by phase B (16 bytes)
-    double prodS;     // product of the m-2 pivots with the prefix's sign parity applied
-    unsigned lo;      // first pair (in the prefix's pair order) inside the call's rank range
-    unsigned rt;      // r | toff << kRBits: r = n - 1 - c_{m-3} columns after the prefix, toff its first slot
-};
-static_assert(sizeof(PairHdr) == 16, "pair header size");
-constexpr int kRBits = 11;
-constexpr unsigned kRMask = (1u << kRBits) - 1u;
-
-constexpr int kHdrBytes = kPrefixBlock * (int)sizeof(PairHdr);
-constexpr int kScanBytes = 2 * kPrefixBlock * 4;
-constexpr int kF32Extra = kPrefixBlock * 4 + kPrefixBlock * 16;   // capped ratios, packed prefix columns
-
-// Column strides of the workgroup's matrix copies: odd (in 4- or 8-byte words),
-// so that lanes reading consecutive columns, or runs of an odd number of
-// columns apart, hit different LDS banks.  The float copy keeps the column's
-// reciprocal scale in slot m.
-template <int M> struct SharedLayout {
-    static constexpr int s64 = M | 1;
-    static constexpr int s32 = (M + 1) | 1;
-};
-
-// The LDS binomial slice holds C(x, y) for y <= m (stride m + 1): the prefix
-// unranking reads y <= m-2, the rank of a prefix's first sequence y <= m.
-template <int M, bool F32> __host__ __device__ int shared_common_bytes(int n) {
-    int b = binom_bytes<M + 1>(n) + align16(n * SharedLayout<M>::s64 * 8);
-    if (F32) b += align16(n * SharedLayout<M>::s32 * 4);
-    return b;
-}
 
 // A projected-column slot is 16 bytes: (t0, t1) in double, or in float with the
 // column's pivot max(|t0|, |t1|) and reciprocal scale for the FP32-bulk
@@ -72,7 +41,6 @@ template <int M, bool F32> __host__ __device__ int shared_common_bytes(int n) {
 constexpr int kSlotBytes = 16;
 
 template <int M, bool F32> __host__ __device__ int shared_wave_bytes(int cap) {
-    using T = typename std::conditional<F32, float, double>::type;
     return kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0) + cap * kSlotBytes;
 }
 
@@ -98,63 +66,6 @@ __device__ __forceinline__ void project(const T (&z0)[P], const T (&z1)[P], cons
     }
     t0 = s0;
     t1 = s1;
-}
-
-// Step K of LU with partial pivoting of the m x (m-2) prefix block, column by
-// column (left-looking): column c_K is read in the lane's current row order
-// `rel` (4 bits per position), the earlier steps are applied to it with the
-// stored multipliers L, its pivot is chosen, and an exchange swaps the two rows
-// of L and of the column and is recorded in `rel`, so that later columns are read
-// already exchanged.  Every entry sees the same operations in the same order as
-// in the row-by-row (right-looking) form, P A = L U, with only L kept: U enters
-// through the pivot product.
-template <int M, int P, int K, typename T, bool CHECK>
-__device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int stride, const int (&c)[P], double& prod,
-                                           bool& neg, float& ratio, unsigned long long& rel) {
-    if constexpr (K < P) {
-        const T* colp = src + c[K] * stride;
-        T x[M];
-#pragma unroll
-        for (int i = 0; i < M; ++i) x[i] = colp[(int)((rel >> (4 * i)) & 15ull)];
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-#pragma unroll
-            for (int i = k + 1; i < M; ++i) x[i] = fma_t(-L[i][k], x[k], x[i]);
-        }
-        unsigned best = pivot_key(x[K], K);
-#pragma unroll
-        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(x[i], i));
-        const int p = pivot_row(best);
-        neg ^= (p != K);
-        if (__ballot(p != K)) {
-            const unsigned long long d = ((rel >> (4 * K)) ^ (rel >> (4 * p))) & 15ull;
-            rel ^= (d << (4 * K)) | (d << (4 * p));
-        }
-#pragma unroll
-        for (int i = K + 1; i < M; ++i) {
-            const bool e = (p == i);
-            if (__ballot(e)) {
-                {
-                    const T u = x[K], v = x[i];
-                    x[K] = e ? v : u;
-                    x[i] = e ? u : v;
-                }
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const T u = L[K][k], v = L[i][k];
-                    L[K][k] = e ? v : u;
-                    L[i][k] = e ? u : v;
-                }
-            }
-        }
-        const T piv = x[K];
-        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)colp[M]);
-        prod *= (double)piv;
-        const T rp = piv == T(0) ? T(0) : recip(piv);   // a zero pivot column: every minor is 0
-#pragma unroll
-        for (int i = K + 1; i < M; ++i) L[i][K] = x[i] * rp;
-        left_steps<M, P, K + 1, T, CHECK>(L, src, stride, c, prod, neg, ratio, rel);
-    }
 }
 
 template <int M, bool F32>

@@ -12,7 +12,6 @@
 
 namespace radic {
 
-constexpr int kPrefixBlock = 64;
 
 // Prefix number pi to its columns c_0 < ... < c_{m-3}, through the
 // combinatorial number system: with x_k = n - 3 - c_k (strictly decreasing),
@@ -52,22 +51,23 @@ __device__ __forceinline__ void unrank_prefix(unsigned long long pi, int n, unsi
     }
 }
 
-// Dictionary rank of the first sequence with prefix number pi, (c, c_{m-3}+1,
-// c_{m-3}+2); J.total when pi is past the last prefix.  Reads the LDS binomial
-// slice bt[x*M + y] = C(x, y).
-template <int M, class Job>
+// Dictionary rank of the first sequence with prefix number pi: the prefix c of
+// m-KT columns (numbered among the (m-KT)-subsets of the first n-KT columns)
+// followed by c_last+1, ..., c_last+KT; J.total when pi is past the last
+// prefix.  Reads the LDS binomial slice bt[x*stride + y] = C(x, y), y < m-KT.
+template <int M, class Job, int KT = 2>
 __device__ unsigned long long first_completion_rank(unsigned long long pi, const Job& J,
                                                     const unsigned long long* bt, int stride = M) {
-    constexpr int P = M - 2;
+    constexpr int P = M - KT;
     if (pi >= J.n_prefix) return J.total;
     const int n = J.n;
     int c[P];
-    unrank_prefix<P>(pi, n, J.n_prefix, bt, stride, c);
+    unrank_prefix<P>(pi, n - KT + 2, J.n_prefix, bt, stride, c);
     int full[M];
 #pragma unroll
     for (int k = 0; k < P; ++k) full[k] = c[k];
-    full[P] = c[P - 1] + 1;
-    full[P + 1] = c[P - 1] + 2;
+#pragma unroll
+    for (int j = 0; j < KT; ++j) full[P + j] = c[P - 1] + 1 + j;
     // dictionary rank from the complement count: the sequences after `full`
     // number sum_k C(n-1-c_k, M-k), read from the full binomial table
     unsigned long long after = 0;
@@ -122,15 +122,16 @@ __device__ unsigned long long prefix_of_rank(unsigned long long q, int n, const 
     return pi;
 }
 
-// Ranks [lo, hi) owned by prefix block blk, clipped to the call's rank range.
-template <int M, class Job>
+// Ranks [lo, hi) owned by prefix block blk (BLOCK prefixes of m-KT columns),
+// clipped to the call's rank range.
+template <int M, class Job, int KT = 2, int BLOCK = kPrefixBlock>
 __device__ void prefix_block_ranks(const Job& J, const unsigned long long* bt, unsigned long long blk,
                                    unsigned long long& lo, unsigned long long& hi) {
-    const unsigned long long pi0 = J.p_begin + blk * kPrefixBlock;
-    const unsigned long long pe = pi0 + kPrefixBlock;
+    const unsigned long long pi0 = J.p_begin + blk * BLOCK;
+    const unsigned long long pe = pi0 + BLOCK;
     const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
-    lo = first_completion_rank<M>(pi0, J, bt);
-    hi = first_completion_rank<M>(pi1, J, bt);
+    lo = first_completion_rank<M, Job, KT>(pi0, J, bt);
+    hi = first_completion_rank<M, Job, KT>(pi1, J, bt);
     const unsigned long long qe = J.q_begin + J.count;
     if (lo < J.q_begin) lo = J.q_begin;
     if (hi > qe) hi = qe;

@@ -55,6 +55,10 @@ int float_lds_bytes(int m, int n, int prec, int waves);
 hipError_t upload_binomials_shared(const unsigned long long* host_table);
 int shared_lds(int m, int n, int prec, int waves, int cap);
 hipError_t launch_shared(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s);
+hipError_t upload_binomials_shared3(const unsigned long long* host_table);
+int shared3_lds(int m, int n, int prec, int waves, int cap);
+int shared3_slot_bytes(int prec);
+hipError_t launch_shared3(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s);
 
 constexpr int kBinomRows = RADIC_MAX_N + 1;
 constexpr int kBinomCols = 33;
@@ -170,6 +174,7 @@ static int ensure_device(int* lds_limit = nullptr) {
     if (ue == hipSuccess) ue = upload_binomials_int(t.data());
     if (ue == hipSuccess) ue = upload_binomials_batched(t.data());
     if (ue == hipSuccess) ue = upload_binomials_shared(t.data());
+    if (ue == hipSuccess) ue = upload_binomials_shared3(t.data());
     if (ue == hipSuccess) ue = upload_binomials_wide(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
     g_dev_ready[dev] = true;
@@ -320,18 +325,18 @@ static void host_unrank0(int m, int n, unsigned long long q, int* cols) {
     }
 }
 
-// Number of the prefix (first m-2 columns) of the sequence of rank q, in the
-// dictionary order of the (m-2)-subsets of the first n-2 columns.
-static unsigned long long host_prefix_index(int m, int n, unsigned long long q) {
+// Number of the prefix (first m-kt columns) of the sequence of rank q, in the
+// dictionary order of the (m-kt)-subsets of the first n-kt columns.
+static unsigned long long host_prefix_index(int m, int n, unsigned long long q, int kt) {
     int cols[RADIC_MAX_M];
     host_unrank0(m, n, q, cols);
-    const int P = m - 2;
+    const int P = m - kt;
     unsigned long long r = 0;
     int prev = -1;
     for (int k = 0; k < P; ++k) {
         for (int v = prev + 1; v < cols[k]; ++v) {
             unsigned long long w = 0;
-            host_binomial(n - 3 - v, P - 1 - k, &w);
+            host_binomial(n - kt - 1 - v, P - 1 - k, &w);
             r += w;
         }
         prev = cols[k];
@@ -339,28 +344,36 @@ static unsigned long long host_prefix_index(int m, int n, unsigned long long q) 
     return r;
 }
 
-// The prefix-shared kernels cover 3 <= m <= 12; FP64 stops at 10, where the
-// prefix block no longer fits the register file.
-static bool shared_eligible(int m, int prec) {
+// The float enumeration of a call: 0 per-minor, 2 prefix-shared (minors with
+// equal first m-2 columns share those LU steps), 3 group-shared (equal first
+// m-3 columns).  The shared kernels cover 3 <= m <= 12 (group-shared from
+// m = 4); FP64 stops at 10, where the prefix block no longer fits the register
+// file.  The automatic choice is prefix-shared (measured at least as fast as
+// group-shared on the 8 x 32 workload).
+static int float_enumeration(int m, int n, int prec) {
     int mode;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         mode = g_enumeration;
     }
-    if (mode == RADIC_ENUM_PER_MINOR) return false;
-    return m >= 3 && (prec == RADIC_FP32_BULK ? m <= 12 : m <= 10);
+    if (mode == RADIC_ENUM_PER_MINOR) return 0;
+    const bool ok2 = m >= 3 && (prec == RADIC_FP32_BULK ? m <= 12 : m <= 10);
+    const bool ok3 = ok2 && m >= 4;
+    if (mode == RADIC_ENUM_GROUP_SHARED) return ok3 ? 3 : (ok2 ? 2 : 0);
+    return ok2 ? 2 : 0;
 }
 
 // Projected-column slots per wave: what the workgroup LDS budget leaves after
-// the per-wave records, at least one prefix of the widest kind (n - m + 2
-// columns) and at most what a block of 64 prefixes can fill.
-static int shared_cap(int m, int n, int prec, int waves, int lds_limit) {
-    const int need = n - m + 2;
-    const int slot = 16;   // bytes per projected-column slot
-    const int fixed = shared_lds(m, n, prec, waves, 0);
+// the per-wave records, at least one prefix of the widest kind (n - m + kt
+// columns) and at most what a block of prefixes can fill.
+static int shared_cap(int kt, int m, int n, int prec, int waves, int lds_limit) {
+    const int need = n - m + kt;
+    const int slot = kt == 2 ? 16 : shared3_slot_bytes(prec);   // bytes per projected-column slot
+    const int fixed = kt == 2 ? shared_lds(m, n, prec, waves, 0) : shared3_lds(m, n, prec, waves, 0);
     const int budget = kSharedLds < lds_limit ? kSharedLds : lds_limit;
     int cap = (budget - fixed) / (waves * slot);
-    if (cap > 64 * need) cap = 64 * need;
+    const int most = (kt == 2 ? kPrefixBlock : kGroupBlock) * need;
+    if (cap > most) cap = most;
     return cap > need ? cap : need;
 }
 
@@ -433,24 +446,29 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     J.fb_entries = reinterpret_cast<unsigned*>(ws + ws_fb_entries());
     J.total = total;
     int grid = grid_for(J.chunks, sh.block);
-    bool shared = shared_eligible(m, prec);
+    const int kt = float_enumeration(m, n, prec);
+    bool shared = kt != 0;
     if (shared) {
-        J.mapping = 1;
-        host_binomial(n - 2, m - 2, &J.n_prefix);
-        J.p_begin = host_prefix_index(m, n, q_begin);
-        J.p_end = host_prefix_index(m, n, q_begin + count - 1) + 1;
+        auto lds = [&](int waves, int cap) {
+            return kt == 2 ? shared_lds(m, n, prec, waves, cap) : shared3_lds(m, n, prec, waves, cap);
+        };
+        J.mapping = kt - 1;
+        host_binomial(n - kt, m - kt, &J.n_prefix);
+        J.p_begin = host_prefix_index(m, n, q_begin, kt);
+        J.p_end = host_prefix_index(m, n, q_begin + count - 1, kt) + 1;
         int block = sh.block;
-        J.cap = shared_cap(m, n, prec, block / kWave, lds_limit);
-        while (block > kWave && shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
+        J.cap = shared_cap(kt, m, n, prec, block / kWave, lds_limit);
+        while (block > kWave && lds(block / kWave, J.cap) > lds_limit) {
             block -= kWave;
-            J.cap = shared_cap(m, n, prec, block / kWave, lds_limit);
+            J.cap = shared_cap(kt, m, n, prec, block / kWave, lds_limit);
         }
-        if (shared_lds(m, n, prec, block / kWave, J.cap) > lds_limit) {
+        if (lds(block / kWave, J.cap) > lds_limit) {
             shared = false;
             J.mapping = 0;
         } else {
             sh.block = block;
-            const unsigned long long blocks = (J.p_end - J.p_begin + 63) / 64;
+            const unsigned long long per_block = kt == 2 ? kPrefixBlock : kGroupBlock;
+            const unsigned long long blocks = (J.p_end - J.p_begin + per_block - 1) / per_block;
             const unsigned long long wpb = (unsigned long long)(block / kWave);
             unsigned long long g = (blocks + wpb - 1) / wpb;
             grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
@@ -461,8 +479,9 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     hipError_t e;
     {
         ProfScope ps(stream);
-        e = shared ? launch_shared(m, prec, J, grid, sh.block, stream)
-                   : launch_float(m, prec, false, J, grid, sh.block, stream);
+        e = !shared ? launch_float(m, prec, false, J, grid, sh.block, stream)
+                    : (kt == 2 ? launch_shared(m, prec, J, grid, sh.block, stream)
+                               : launch_shared3(m, prec, J, grid, sh.block, stream));
     }
     if (e != hipSuccess) return device_error("launch of the enumeration kernel", e);
     if (defer) {
@@ -1050,7 +1069,8 @@ int radic_host_unrank(int m, int n, uint64_t q, int* hCols) {
 }
 
 int radic_set_enumeration(int mode) {
-    if (mode != RADIC_ENUM_AUTO && mode != RADIC_ENUM_PER_MINOR && mode != RADIC_ENUM_PREFIX_SHARED)
+    if (mode != RADIC_ENUM_AUTO && mode != RADIC_ENUM_PER_MINOR && mode != RADIC_ENUM_PREFIX_SHARED &&
+        mode != RADIC_ENUM_GROUP_SHARED)
         return RADIC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
     g_enumeration = mode;

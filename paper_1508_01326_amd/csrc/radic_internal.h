@@ -11,6 +11,8 @@ namespace radic {
 constexpr int kWave = 64;            // CDNA4 wavefront width
 constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration kernel
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
+constexpr int kPrefixBlock = 64;     // prefixes of m-2 columns per wave block (prefix-shared kernels)
+constexpr int kGroupBlock = 16;      // prefixes of m-3 columns per wave block (group-shared kernel)
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
 constexpr int kDeferEntries = 1 << 22;   // 16-byte deferral entries in a single-matrix workspace
@@ -53,13 +55,14 @@ struct FloatJob {
     unsigned* fb_count;
     unsigned* fb_entries;
     Partial* fb_partials;
-    // Prefix-shared enumeration (m >= 3): the ranks are grouped by their first
-    // m-2 columns ("prefixes", numbered in dictionary order among the
-    // (m-2)-subsets of the first n-2 columns); waves take blocks of prefixes.
-    int mapping;                  // 0: lane chunks of ranks; 1: blocks of prefixes
-    int cap;                      // projected-column slots per wave (mapping 1)
+    // Prefix-shared enumeration: the ranks are grouped by their first m-2
+    // (mapping 1, m >= 3) or m-3 (mapping 2, m >= 4) columns ("prefixes",
+    // numbered in dictionary order among the (m-k)-subsets of the first n-k
+    // columns); waves take blocks of prefixes.
+    int mapping;                  // 0: lane chunks of ranks; 1: blocks of m-2 column prefixes; 2: of m-3
+    int cap;                      // projected-column slots per wave (mappings 1, 2)
     unsigned long long total;     // C(n, m)
-    unsigned long long n_prefix;  // C(n-2, m-2)
+    unsigned long long n_prefix;  // C(n-2, m-2) (mapping 1) or C(n-3, m-3) (mapping 2)
     unsigned long long p_begin;   // prefixes [p_begin, p_end) cover [q_begin, q_begin + count)
     unsigned long long p_end;
 };

@@ -1,0 +1,103 @@
+// Pieces shared by the prefix-shared floating-point kernels: the per-wave
+// prefix records, the workgroup's LDS copies of the matrix, and the pivoted LU
+// of a prefix's m x P block.
+#pragma once
+
+#include <type_traits>
+
+#include "prefix.h"
+#include "stage.h"
+
+namespace radic {
+
+// Per-prefix record in the wave's LDS, read by the minor loop (16 bytes).  A
+// prefix here is the first m-k columns (k = 2 or 3 trailing columns).
+struct PairHdr {
+    double prodS;     // product of the prefix's pivots with its sign parity applied
+    unsigned lo;      // first minor (in the prefix's own order) inside the call's rank range
+    unsigned rt;      // r | toff << kRBits: r columns after the prefix, toff its first slot
+};
+static_assert(sizeof(PairHdr) == 16, "pair header size");
+constexpr int kRBits = 11;
+constexpr unsigned kRMask = (1u << kRBits) - 1u;
+
+constexpr int kHdrBytes = kPrefixBlock * (int)sizeof(PairHdr);
+constexpr int kScanBytes = 2 * kPrefixBlock * 4;
+constexpr int kF32Extra = kPrefixBlock * 4 + kPrefixBlock * 16;   // FP32-bulk: capped ratios, packed prefix columns
+
+// Column strides of the workgroup's matrix copies: odd (in 4- or 8-byte words),
+// so that lanes reading consecutive columns, or runs of an odd number of
+// columns apart, hit different LDS banks.  The float copy keeps the column's
+// reciprocal scale in slot m.
+template <int M> struct SharedLayout {
+    static constexpr int s64 = M | 1;
+    static constexpr int s32 = (M + 1) | 1;
+};
+
+// The LDS binomial slice holds C(x, y) for y <= m (stride m + 1): the prefix
+// unranking reads y <= m-2, the rank of a prefix's first sequence y <= m.  Then
+// the double copy and, for FP32-bulk, the row-scaled float copy.
+template <int M, bool F32> __host__ __device__ int shared_common_bytes(int n) {
+    int b = binom_bytes<M + 1>(n) + align16(n * SharedLayout<M>::s64 * 8);
+    if (F32) b += align16(n * SharedLayout<M>::s32 * 4);
+    return b;
+}
+
+// Step K of LU with partial pivoting of the m x P prefix block, column by
+// column (left-looking): column c_K is read in the lane's current row order
+// `rel` (4 bits per position), the earlier steps are applied to it with the
+// stored multipliers L, its pivot is chosen, and an exchange swaps the two rows
+// of L and of the column and is recorded in `rel`, so that later columns are read
+// already exchanged.  Every entry sees the same operations in the same order as
+// in the row-by-row (right-looking) form, P A = L U, with only L kept: U enters
+// through the pivot product.
+template <int M, int P, int K, typename T, bool CHECK>
+__device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int stride, const int (&c)[P], double& prod,
+                                           bool& neg, float& ratio, unsigned long long& rel) {
+    if constexpr (K < P) {
+        const T* colp = src + c[K] * stride;
+        T x[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) x[i] = colp[(int)((rel >> (4 * i)) & 15ull)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = k + 1; i < M; ++i) x[i] = fma_t(-L[i][k], x[k], x[i]);
+        }
+        unsigned best = pivot_key(x[K], K);
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) best = max(best, pivot_key(x[i], i));
+        const int p = pivot_row(best);
+        neg ^= (p != K);
+        if (__ballot(p != K)) {
+            const unsigned long long d = ((rel >> (4 * K)) ^ (rel >> (4 * p))) & 15ull;
+            rel ^= (d << (4 * K)) | (d << (4 * p));
+        }
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) {
+            const bool e = (p == i);
+            if (__ballot(e)) {
+                {
+                    const T u = x[K], v = x[i];
+                    x[K] = e ? v : u;
+                    x[i] = e ? u : v;
+                }
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const T u = L[K][k], v = L[i][k];
+                    L[K][k] = e ? v : u;
+                    L[i][k] = e ? u : v;
+                }
+            }
+        }
+        const T piv = x[K];
+        if (CHECK) ratio *= __saturatef(__builtin_fabsf((float)piv) * (float)colp[M]);
+        prod *= (double)piv;
+        const T rp = piv == T(0) ? T(0) : recip(piv);   // a zero pivot column: every minor is 0
+#pragma unroll
+        for (int i = K + 1; i < M; ++i) L[i][K] = x[i] * rp;
+        left_steps<M, P, K + 1, T, CHECK>(L, src, stride, c, prod, neg, ratio, rel);
+    }
+}
+
+}  // namespace radic

@@ -109,9 +109,9 @@ def test_launch_and_tau_setters_validate():
     assert L.radic_set_fallback_tau(float("nan")) == radic.RADIC_EINVAL
     assert L.radic_set_fallback_tau(-1.0) == radic.RADIC_EINVAL
     assert L.radic_set_fallback_tau(1.0 / 1024) == radic.RADIC_OK
-    assert L.radic_set_enumeration(3) == radic.RADIC_EINVAL
+    assert L.radic_set_enumeration(4) == radic.RADIC_EINVAL
     assert L.radic_set_enumeration(-1) == radic.RADIC_EINVAL
-    for mode in ("per_minor", "prefix_shared", "auto"):
+    for mode in ("per_minor", "prefix_shared", "group_shared", "auto"):
         radic.set_enumeration(mode)
 
 

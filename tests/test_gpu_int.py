@@ -103,7 +103,7 @@ def test_capacity_too_small():
         assert rc == radic.RADIC_OK
 
 
-@pytest.mark.parametrize("mode", ["per_minor", "prefix_shared"])
+@pytest.mark.parametrize("mode", ["per_minor", "prefix_shared", "group_shared"])
 def test_enumerations_bit_exact(mode):
     # the prefix-shared exact kernel (minors sharing their first m-2 columns share
     # those fraction-free elimination steps mod p) and the per-minor kernel

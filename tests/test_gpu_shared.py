@@ -1,6 +1,9 @@
-"""GPU parity of the prefix-shared enumeration (minors with equal first m-2
-columns share the first m-2 steps of their pivoted LU) against the oracle, and
-against the per-minor enumeration on the same inputs.
+"""GPU parity of the shared enumerations against the oracle, and against the
+per-minor enumeration on the same inputs: prefix-shared (minors with equal first
+m-2 columns share the first m-2 steps of their pivoted LU, each minor ends with a
+2 x 2 determinant) and group-shared (equal first m-3 columns share m-3 steps,
+each minor ends with a 3 x 3 determinant as a dot with a cross product).  Every
+test runs under both; group-shared falls back to prefix-shared for m = 3.
 
 Every case prints its identity before the GPU call so a failing run names it."""
 import math
@@ -18,19 +21,19 @@ pytestmark = pytest.mark.gpu
 radic = pytest.importorskip("paper_1508_01326_amd")
 
 
-@pytest.fixture(autouse=True)
-def _reset():
+@pytest.fixture(autouse=True, params=["prefix_shared", "group_shared"])
+def mode(request):
     radic.set_launch(0, 0)
     radic.set_fallback_tau(1.0 / 1024)
-    radic.set_enumeration("prefix_shared")
-    yield
+    radic.set_enumeration(request.param)
+    yield request.param
     radic.set_launch(0, 0)
     radic.set_fallback_tau(1.0 / 1024)
     radic.set_enumeration("auto")
 
 
 def run(A, precision, what, **kw):
-    print(f"[case] shared {what} shape={np.shape(A)} precision={precision}", flush=True)
+    print(f"[case] {what} shape={np.shape(A)} precision={precision}", flush=True)
     return radic.radic_det(to_device(A), precision=precision, **kw)
 
 
@@ -55,10 +58,10 @@ def test_random_shapes(shape, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
-def test_same_as_per_minor(precision):
+def test_same_as_per_minor(precision, mode):
     # both enumerations evaluate every minor; they differ in rounding only
     A = workloads.random_float(8, 24, seed=81)
-    a = run(A, precision, "shared 8x24")
+    a = run(A, precision, f"{mode} 8x24")
     radic.set_enumeration("per_minor")
     b = run(A, precision, "per-minor 8x24")
     ref = oracle.radic_f64(A)
@@ -188,18 +191,19 @@ def test_fallback_near_parallel_columns():
     print("error without fallback / S:", abs(bad["value"] - ref["value"]) / ref["abs_sum"])
 
 
-def test_fallback_columns_beyond_255():
+def test_fallback_columns_beyond_255(mode):
     # flagged minors whose columns exceed one byte: the deferral entries must
     # carry 10-bit column indices
     rng = np.random.default_rng(90)
-    A = rng.standard_normal((3, 300))
-    A[:, 290] = A[:, 280] * (1.0 + 1e-7) + 1e-7 * rng.standard_normal(3)
-    ref = oracle.radic_f64(A)
-    for mode in ("prefix_shared", "per_minor"):
-        radic.set_enumeration(mode)
-        got = run(A, "fp32_bulk", f"columns 280, 290 near-parallel, {mode}")
-        assert got["n_fallback"] >= 298
-        assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-6, f"wide fallback {mode}")
+    for m, n, c0, c1 in ((3, 300, 280, 290), (4, 262, 256, 260)):
+        A = rng.standard_normal((m, n))
+        A[:, c1] = A[:, c0] * (1.0 + 1e-7) + 1e-7 * rng.standard_normal(m)
+        ref = oracle.radic_f64(A)
+        for md in (mode, "per_minor"):
+            radic.set_enumeration(md)
+            got = run(A, "fp32_bulk", f"m={m} columns {c0}, {c1} near-parallel, {md}")
+            assert got["n_fallback"] >= math.comb(n - 2, m - 2)
+            assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-6, f"wide fallback {md}")
 
 
 def test_near_dependent_rows():
@@ -210,7 +214,7 @@ def test_near_dependent_rows():
     assert_close(got["value"], ref["value"], max(ref["abs_sum"], 1e-300), 1e-5, "near-dependent")
 
 
-def test_workload4_sampled_ranges():
+def test_workload4_sampled_ranges(mode):
     # the 12 x 36 precision-stress matrix (C(36,12) = 1.25e9 minors) on rank
     # windows the oracle finishes quickly: start, middle, end, in both precisions
     A = workloads.single_matrix(4)
@@ -221,7 +225,7 @@ def test_workload4_sampled_ranges():
             if prec == "fp64":
                 radic.set_enumeration("auto")   # FP64 m = 12 runs per-minor
             else:
-                radic.set_enumeration("prefix_shared")
+                radic.set_enumeration(mode)
             print(f"[case] workload4 window {q0} {prec}", flush=True)
             r = radic.radic_det_range(to_device(A), q0, 50000, precision=prec)
             assert r["n_subsets"] == 50000
