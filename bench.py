@@ -33,8 +33,8 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # summary and commands are in profiles/k_radic_shared_8x32.md).  They hold for
 # the kernel sources they were taken on: `traffic` is reported only while the
 # sources hash to the same value.
-KERNEL_SOURCES = ["kernels_shared.hip", "prefix.h", "stage.h", "lu_float.h", "enumerate.h", "radic_internal.h"]
-PROFILED_TRAFFIC = {"sources_sha256": "bf65baf91d3976f4a6d7ce445ac65fe8ffa9f19be327a9351e2676a7aac442d6", "fp64": 458221, "fp32_bulk": 1497454}
+KERNEL_SOURCES = ["kernels_shared.hip", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h", "radic_internal.h"]
+PROFILED_TRAFFIC = {"sources_sha256": "9d76f270d555def8b074aea167a7130ea89df0cf1347a0f47179063fc95748e9", "fp64": 386550, "fp32_bulk": 1431926}
 
 
 def kernel_sources_sha256():
@@ -66,20 +66,27 @@ def executed_flops(m, n, enumeration):
     """Floating-point operations one launch performs on the whole C(n, m) rank
     space.  Per minor: GEPP of the m x m minor (m - 1 steps; 2 sum t^2 + sum t +
     (m - 1) = 315 for m = 8) plus the m - 1 multiplications of the pivot
-    product.  Prefix-shared (m >= 3): per prefix the m - 2 steps on the m x (m-2)
-    block, its 2 x (m-2) row solve for W, and the product of its pivots; per later
-    column W x (2m FMAs); per minor the 2 x 2 determinant and the product with
-    the prefix's signed pivot product (4 flops)."""
+    product.  Prefix-shared (m >= 3, P = m - 2): per prefix the P steps on the
+    m x P block, the 2 x P row solve for W, and the product of its pivots; per
+    later column W x (2P FMAs); per minor the 2 x 2 determinant and the product
+    with the prefix's signed pivot product (4 flops).  Group-shared (m >= 4,
+    P = m - 3): per group the P steps, the 3 x P row solve and the pivot
+    product; per later column 3P FMAs; per pair of later columns a cross product
+    (9 flops); per minor the dot product and the pivot product (6 flops)."""
     total = math.comb(n, m)
     if enumeration == "per_minor" or m < 3:
         return (gepp_flops(m, m, m - 1) + (m - 1)) * total
-    P = m - 2
-    per_prefix = gepp_flops(m, P, P) + 2 * P * (P - 1) + P
+    kt = 3 if enumeration == "group_shared" and m >= 4 else 2
+    P = m - kt
+    per_prefix = gepp_flops(m, P, P) + kt * P * (P - 1) + P
     flops = 0
-    for v in range(P - 1, n - 2):            # last prefix column (0-based)
+    for v in range(P - 1, n - kt):           # last prefix column (0-based)
         k = math.comb(v, P - 1)              # prefixes ending at v
         r = n - 1 - v                        # columns after it
-        flops += k * (per_prefix + 4 * m * r + 4 * math.comb(r, 2))
+        if kt == 2:
+            flops += k * (per_prefix + 4 * P * r + 4 * math.comb(r, 2))
+        else:
+            flops += k * (per_prefix + 6 * P * r + 9 * math.comb(r, 2) + 6 * math.comb(r, 3))
     return flops
 
 
@@ -158,7 +165,7 @@ def other_workloads(radic, binding, workloads, torch, dev, args):
 
 
 def traffic_for(form, enumeration):
-    if enumeration == "per_minor" or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
         return None
     return PROFILED_TRAFFIC[form]
 
@@ -166,6 +173,8 @@ def traffic_for(form, enumeration):
 def kernel_name(enumeration, form):
     if enumeration == "per_minor":
         return "k_radic_float<8,true,false,true>" if form == "fp32_bulk" else "k_radic_float<8,false,false,false>"
+    if enumeration == "group_shared":
+        return "k_radic_shared3<8,true>" if form == "fp32_bulk" else "k_radic_shared3<8,false>"
     return "k_radic_shared<8,true>" if form == "fp32_bulk" else "k_radic_shared<8,false>"
 
 
