@@ -410,7 +410,11 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared3(FloatJob J) {
             wave_lds_sync();
         }
     }
-    if (F32 && lane == 0) J.fb_count[gwave] = (unsigned)gcount;   // above J.defer_cap: overflowed
+    if constexpr (F32 && shared_tail_refactor(M)) {
+        shared_fp32_tail<M, 3, kGroupBlock, BS, S64>(J, bt, cd, gcount, gwave, nwaves, nblk, lane, hi, lo, ab, nfb);
+    } else if (F32 && lane == 0) {
+        J.fb_count[gwave] = (unsigned)gcount;   // above J.defer_cap: overflowed
+    }
 
     wave_reduce_partial(hi, lo, ab, nfb);
     if (lane == 0) {

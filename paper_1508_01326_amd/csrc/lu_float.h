@@ -51,6 +51,21 @@ __device__ __forceinline__ void gather(T (&a)[M][M], const T* base, int stride, 
     }
 }
 
+// Double minor gather from a column-major copy with column stride ST64: pairs of
+// rows by 16-byte loads where the stride keeps them aligned, else one by one.
+template <int M, int ST64>
+__device__ __forceinline__ void gather_f64(double (&a)[M][M], const double* base, const int (&col)[M]) {
+    if constexpr (ST64 % 2 == 0) {
+        gather<M, double>(a, base, ST64, col);
+    } else {
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+#pragma unroll
+            for (int i = 0; i < M; ++i) a[i][j] = base[col[j] * ST64 + i];
+        }
+    }
+}
+
 // Bring each lane's pivot row p into row K with selects.  Only candidate rows
 // that some lane of the wave chose are visited (a wave-uniform test), so a step
 // on which the whole wave keeps row K costs one ballot per candidate.  When every
@@ -196,13 +211,12 @@ __device__ __forceinline__ void unpack_cols(const unsigned* w, int (&col)[M]) {
 
 // Signed term of one queued minor refactored in double (rows in natural order,
 // from the row-scaled double copy cd).
-template <int M>
+template <int M, int ST64 = Layout<M>::st64>
 __device__ __forceinline__ double refactor_entry_f64(const double* cd, const unsigned* entry, double& absdet) {
-    constexpr int ST64 = Layout<M>::st64;
     int c[M];
     unpack_cols<M>(entry, c);
     double a[M][M];
-    gather<M, double>(a, cd, ST64, c);
+    gather_f64<M, ST64>(a, cd, c);
     bool neg = radic_sign_odd<M>(c);
     bool flag = false;
     unsigned long long perm = 0;

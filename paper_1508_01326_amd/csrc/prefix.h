@@ -126,12 +126,12 @@ __device__ unsigned long long prefix_of_rank(unsigned long long q, int n, const 
 // clipped to the call's rank range.
 template <int M, class Job, int KT = 2, int BLOCK = kPrefixBlock>
 __device__ void prefix_block_ranks(const Job& J, const unsigned long long* bt, unsigned long long blk,
-                                   unsigned long long& lo, unsigned long long& hi) {
+                                   unsigned long long& lo, unsigned long long& hi, int stride = M) {
     const unsigned long long pi0 = J.p_begin + blk * BLOCK;
     const unsigned long long pe = pi0 + BLOCK;
     const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
-    lo = first_completion_rank<M, Job, KT>(pi0, J, bt);
-    hi = first_completion_rank<M, Job, KT>(pi1, J, bt);
+    lo = first_completion_rank<M, Job, KT>(pi0, J, bt, stride);
+    hi = first_completion_rank<M, Job, KT>(pi1, J, bt, stride);
     const unsigned long long qe = J.q_begin + J.count;
     if (lo < J.q_begin) lo = J.q_begin;
     if (hi > qe) hi = qe;
@@ -139,23 +139,23 @@ __device__ void prefix_block_ranks(const Job& J, const unsigned long long* bt, u
 }
 
 // Every rank of [lo, hi) factored in double by the wave, minor by minor (rows in
-// natural order, from the row-scaled double copy cd): lane l takes the l-th of
-// 64 contiguous sub-ranges.  Counts the ranks in nvalid.
-template <int M>
+// natural order, from the row-scaled double copy cd, column stride ST64): lane l
+// takes the l-th of 64 contiguous sub-ranges.  bt[x*BSTRIDE + y] = C(x, y).
+// Counts the ranks in nvalid.
+template <int M, int BSTRIDE = M, int ST64 = Layout<M>::st64>
 __device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
                                unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
                                double& ab, unsigned long long& nvalid) {
-    constexpr int ST64 = Layout<M>::st64;
     if (hi <= lo) return;
     const unsigned long long per = (hi - lo + kWave - 1) / kWave;
     const unsigned long long s0 = lo + (unsigned long long)lane * per;
     const unsigned long long s1 = s0 + per < hi ? s0 + per : hi;
     const double none[M] = {};
     int col[M];
-    unrank<M>(s0 < hi ? s0 : lo, J.n, bt, col);
+    unrank_strided<M>(s0 < hi ? s0 : lo, J.n, bt, BSTRIDE, col);
     for (unsigned long long s = 0; s < per; ++s) {
         double a[M][M];
-        gather<M, double>(a, cd, ST64, col);
+        gather_f64<M, ST64>(a, cd, col);
         bool neg = radic_sign_odd<M>(col);
         bool flag = false;
         unsigned long long perm = 0;

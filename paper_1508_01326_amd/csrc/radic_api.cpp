@@ -484,11 +484,14 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
                                : launch_shared3(m, prec, J, grid, sh.block, stream));
     }
     if (e != hipSuccess) return device_error("launch of the enumeration kernel", e);
-    if (defer) {
+    // the shared kernels refactor their flagged minors at the end of each
+    // workgroup up to m = 8; otherwise the refactorisation kernel does
+    const bool refactor = defer && !(shared && shared_tail_refactor(m));
+    if (refactor) {
         e = launch_refactor(m, J, grid, sh.block, stream);
         if (e != hipSuccess) return device_error("launch of the refactorisation kernel", e);
     }
-    e = launch_finalize_float(J.partials, grid, defer ? J.fb_partials : nullptr, refactor_grid(grid, sh.block),
+    e = launch_finalize_float(J.partials, grid, refactor ? J.fb_partials : nullptr, refactor_grid(grid, sh.block),
                               J.header, dOut, count, defer, stream);
     return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
 }

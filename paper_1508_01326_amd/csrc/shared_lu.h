@@ -100,4 +100,37 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
     }
 }
 
+
+// FP32-bulk tail of a prefix-shared wave.  The wave queued its flagged minors in
+// its segment of J.fb_entries (gcount, wave-uniform).  If they fit, its lanes
+// refactor them in double, one per lane, and add them to their sums; otherwise
+// the wave drops its float sums and redoes its own blocks (BLOCK prefixes of
+// m-KT columns: gwave, gwave + nwaves, ...) in double.  Reads the binomial slice
+// bt (stride BS) and the row-scaled double copy cd (column stride S64).
+template <int M, int KT, int BLOCK, int BS, int S64>
+__device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt, const double* cd, int gcount,
+                                 unsigned long long gwave, unsigned long long nwaves, unsigned long long nblk,
+                                 int lane, double& hi, double& lo, double& ab, unsigned long long& nfb) {
+    if (gcount > J.defer_cap) {
+        hi = lo = ab = 0.0;
+        nfb = 0;
+        for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
+            unsigned long long r0, r1;
+            prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
+            redo_ranks_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+        }
+        return;
+    }
+    const unsigned* seg = J.fb_entries + (size_t)gwave * J.defer_cap * 4;
+    for (int e = lane; e < gcount; e += kWave) {
+        double ad;
+        const double term = refactor_entry_f64<M, S64>(cd, seg + 4 * e, ad);
+        double sum, err;
+        two_sum(hi, term, sum, err);
+        hi = sum;
+        lo += err;
+        ab += ad;
+    }
+}
+
 }  // namespace radic
