@@ -322,16 +322,42 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                                   : ((float)tau > 0.f ? (float)tau * ta.z * __builtin_amdgcn_rcpf(h2) : 0.f);
                     }
                 };
-                if constexpr (F32) threshold();
-                for (unsigned k = 0; k < chunk; ++k) {
-                    const bool valid = k < kend;
-                    const TV tb = tv[toff + ib];
-                    // signed 2 x 2 determinant: (-1)^(ia+ib) is carried by the stored columns
-                    const T d = fma_t(ta.x, tb.y, -(ta.y * tb.x));
-                    bool keep = valid;
-                    if constexpr (F32) {
-                        const bool flag = valid && (fabsf(d) * tb.w < thr);
-                        keep = valid && !flag;
+                if constexpr (!F32) {
+                    // each lane walks exactly its share; both columns are read
+                    // every step (no loop-carried column, no copies)
+                    for (unsigned k = 0; k < kend; ++k) {
+                        const TV ta2 = tv[toff + ia];
+                        const TV tb = tv[toff + ib];
+                        const T d = fma_t(ta2.x, tb.y, -(ta2.y * tb.x));
+                        const double term = (double)d * h.prodS;
+                        double sum, err;
+                        two_sum(hi, term, sum, err);
+                        hi = sum;
+                        lo += err;
+                        ab += fabs(term);
+                        if (++ib >= hr) {
+                            ++ia;
+                            ib = ia + 1;
+                            if (ib >= hr) {
+                                s = min(s + 1, ntake - 1);
+                                h = hdr[s];
+                                hr = (int)(h.rt & kRMask);
+                                toff = (int)(h.rt >> kRBits);
+                                ia = 0;
+                                ib = 1;
+                            }
+                        }
+                    }
+                }
+                if constexpr (F32) {
+                    threshold();
+                    // as above, each lane walks its share; the flagged-minor count
+                    // stays exact on the lanes still walking (every ballot of a step
+                    // is seen by all of them) and is made wave-uniform after the loop
+                    for (unsigned k = 0; k < kend; ++k) {
+                        const TV tb = tv[toff + ib];
+                        const T d = fma_t(ta.x, tb.y, -(ta.y * tb.x));
+                        const bool flag = fabsf(d) * tb.w < thr;
                         const unsigned long long fm = __ballot(flag);
                         if (fm) {
                             const int pos = gcount + (int)__builtin_amdgcn_mbcnt_hi(
@@ -352,34 +378,36 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                             }
                             gcount += __popcll(fm);
                         }
-                    }
-                    // a minor outside the lane's share, or queued, adds an exact 0
-                    const double term = keep ? (double)d * h.prodS : 0.0;
-                    double sum, err;
-                    two_sum(hi, term, sum, err);
-                    hi = sum;
-                    lo += err;
-                    ab += fabs(term);
-                    // next pair; past the prefix's last pair, the next prefix
-                    if (++ib >= hr) {
-                        ++ia;
-                        ib = ia + 1;
-                        if (ib >= hr) {
-                            s = min(s + 1, ntake - 1);
-                            h = hdr[s];
-                            hr = (int)(h.rt & kRMask);
-                            toff = (int)(h.rt >> kRBits);
-                            if (F32) hratio = ratios[s];
-                            ia = 0;
-                            ib = 1;
+                        // a queued minor adds an exact 0
+                        const double term = flag ? 0.0 : (double)d * h.prodS;
+                        double sum, err;
+                        two_sum(hi, term, sum, err);
+                        hi = sum;
+                        lo += err;
+                        ab += fabs(term);
+                        // next pair; past the prefix's last pair, the next prefix
+                        if (++ib >= hr) {
+                            ++ia;
+                            ib = ia + 1;
+                            if (ib >= hr) {
+                                s = min(s + 1, ntake - 1);
+                                h = hdr[s];
+                                hr = (int)(h.rt & kRMask);
+                                toff = (int)(h.rt >> kRBits);
+                                hratio = ratios[s];
+                                ia = 0;
+                                ib = 1;
+                            }
+                            ta = tv[toff + ia];
+                            threshold();
                         }
-                        ta = tv[toff + ia];
-                        if constexpr (F32) threshold();
                     }
+#pragma unroll
+                    for (int o = kWave / 2; o > 0; o >>= 1) gcount = max(gcount, __shfl_xor(gcount, o, kWave));
                 }
             }
-            // a full segment: the workgroup is redone in double by the
-            // refactorisation kernel, so the rest is not needed
+            // a full segment: the wave's blocks are redone in double (by the wave
+            // at its end, or by the refactorisation kernel), so the rest is not needed
             if (F32 && gcount > J.defer_cap) overflow = true;
             next += (unsigned long long)ntake;
             wave_lds_sync();
