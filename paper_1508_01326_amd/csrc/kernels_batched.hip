@@ -366,7 +366,7 @@ constexpr int kBatchCap = 256;   // projected-column slots per wave (prefix-shar
 template <int M> struct IntWaveLds {
     double cr[kBatchMaxN * IntLayout<M>::st];
     IntSlot slot[M >= 3 && M <= 10 ? kPrefixBlock : 1];
-    unsigned incl[M >= 3 && M <= 10 ? kPrefixBlock : 1];
+    unsigned incl[M >= 3 && M <= 10 ? 2 * kPrefixBlock : 1];   // pair and column scans
     double2 tv[M >= 3 && M <= 10 ? kBatchCap : 1];
 };
 

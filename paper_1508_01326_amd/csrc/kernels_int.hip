@@ -170,7 +170,7 @@ struct IntSharedJob {
 
 template <int M> __host__ __device__ int int_shared_lds_bytes(int n, int waves, int cap) {
     return binom_bytes<M>(n) + align16(n * IntLayout<M>::st * 8) +
-           waves * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 4 + align16(cap * 16));
+           waves * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 8 + align16(cap * 16));
 }
 
 template <int M>
@@ -186,10 +186,10 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
     unsigned long long* bt = reinterpret_cast<unsigned long long*>(smem);
     double* cr = reinterpret_cast<double*>(smem + binom_bytes<M>(n));
     unsigned char* wr = smem + binom_bytes<M>(n) + align16(n * ST * 8) +
-                        wave * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 4 + align16(J.cap * 16));
+                        wave * (kPrefixBlock * (int)sizeof(IntSlot) + kPrefixBlock * 8 + align16(J.cap * 16));
     IntSlot* slot = reinterpret_cast<IntSlot*>(wr);
     unsigned* incl = reinterpret_cast<unsigned*>(wr + kPrefixBlock * sizeof(IntSlot));
-    double2* tv = reinterpret_cast<double2*>(wr + kPrefixBlock * sizeof(IntSlot) + kPrefixBlock * 4);
+    double2* tv = reinterpret_cast<double2*>(wr + kPrefixBlock * sizeof(IntSlot) + kPrefixBlock * 8);
 
     stage_binomials<M>(bt, n);
     for (int e = threadIdx.x; e < M * n; e += blockDim.x) {

@@ -7,9 +7,11 @@
 // the pivot by the pivot u_k and subtracts multiples of the pivot row, and its
 // pivot (the first nonzero entry of column k) and multipliers depend on the
 // first k+1 columns only.  Per prefix a lane eliminates the m x (m-2) block
-// and forms the two rows W (2 x m) of the fraction-free elimination operator
-// that produce rows m-2, m-1; it writes t_c = W x_c mod p for every later
-// column c to LDS.  For a minor with later columns a < b,
+// (column by column, keeping only the multipliers) and forms the two rows W
+// (2 x m) of the fraction-free elimination operator that produce rows m-2,
+// m-1; the round's later columns are then split over the lanes, which fetch W
+// from the owner lane and write t_c = W x_c mod p to LDS.  For a minor with
+// later columns a < b,
 //     det = (t_a0 t_b1 - t_a1 t_b0) / prod_{k<m-2} P_k   (mod p),
 // P_k = u_0 ... u_k the running pivot products (the last two elimination steps
 // of the minor, written out), with the sign of the prefix's row exchanges.  The
@@ -42,49 +44,69 @@ __device__ __forceinline__ double dot_mod(const double (&w)[M], const double (&x
     return mod_fix(__builtin_fma(-q, p, s), p);
 }
 
-// Step K of the prefix's fraction-free elimination: pivot = first row >= K with
-// a nonzero entry; whole rows exchanged (the column-K entries below the pivot
-// are kept as the step's multipliers); the lane's row order tracked in rel.
+// Step K of the prefix's fraction-free elimination, column by column
+// (left-looking).  Column c_K is read in the lane's current row order `rel` (4
+// bits per position), the earlier steps are applied to it (x_i <- u_k x_i -
+// L_ik x_k for i > k, k = 0, 1, ...), its pivot is the first row >= K with a
+// nonzero entry, and an exchange swaps the two rows of L and of the column and
+// is recorded in rel, so that later columns are read already exchanged.  L_iK
+// keeps the column's entries below the pivot (the step's multipliers).  Every
+// residue sees the same operations as in the row-by-row form.
 template <int M, int P, int K>
-__device__ __forceinline__ void int_prefix_steps(double (&a)[M][P], double (&u)[P], double p, double pinv,
-                                                 double& Pk, double& D, bool& zero, bool& neg,
-                                                 unsigned long long& rel) {
+__device__ __forceinline__ void int_left_steps(double (&L)[M][P], double (&u)[P], const double* cr, int stride,
+                                               const int (&c)[P], double p, double pinv, double& Pk, double& D,
+                                               bool& zero, bool& neg, unsigned long long& rel) {
     if constexpr (K < P) {
+        const double* colp = cr + c[K] * stride;
+        double x[M];
+#pragma unroll
+        for (int i = 0; i < M; ++i) x[i] = colp[(int)((rel >> (4 * i)) & 15ull)];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int i = k + 1; i < M; ++i) {
+                x[i] = submod(mulmod(u[k], x[i], p, pinv), mulmod(L[i][k], x[k], p, pinv), p);
+                // an empty register constraint: keeps the compiler's instruction
+                // combining from folding the whole chain of reductions (whose
+                // compile time otherwise explodes from m = 8); no code
+                asm volatile("" : "+v"(x[i]));
+            }
+        }
         unsigned best = 0;
 #pragma unroll
-        for (int i = K; i < M; ++i) best = max(best, a[i][K] != 0.0 ? (unsigned)(15 - i) : 0u);
+        for (int i = K; i < M; ++i) best = max(best, x[i] != 0.0 ? (unsigned)(15 - i) : 0u);
         const bool col_zero = (best == 0u);
         const int pr = col_zero ? K : 15 - (int)best;
         zero |= col_zero;
         neg ^= (pr != K);
         if (__ballot(pr != K)) {
-            const unsigned long long x = ((rel >> (4 * K)) ^ (rel >> (4 * pr))) & 15ull;
-            rel ^= (x << (4 * K)) | (x << (4 * pr));
+            const unsigned long long d = ((rel >> (4 * K)) ^ (rel >> (4 * pr))) & 15ull;
+            rel ^= (d << (4 * K)) | (d << (4 * pr));
 #pragma unroll
             for (int i = K + 1; i < M; ++i) {
-                const bool c = (pr == i);
-                if (__ballot(c)) {
+                const bool e = (pr == i);
+                if (__ballot(e)) {
+                    {
+                        const double v0 = x[K], v1 = x[i];
+                        x[K] = e ? v1 : v0;
+                        x[i] = e ? v0 : v1;
+                    }
 #pragma unroll
-                    for (int j = 0; j < P; ++j) {
-                        const double x0 = a[K][j], y0 = a[i][j];
-                        a[K][j] = c ? y0 : x0;
-                        a[i][j] = c ? x0 : y0;
+                    for (int k = 0; k < K; ++k) {
+                        const double v0 = L[K][k], v1 = L[i][k];
+                        L[K][k] = e ? v1 : v0;
+                        L[i][k] = e ? v0 : v1;
                     }
                 }
             }
         }
-        const double uk = col_zero ? 1.0 : a[K][K];
+        const double uk = col_zero ? 1.0 : x[K];
         u[K] = uk;
         Pk = mulmod(Pk, uk, p, pinv);
         D = mulmod(D, Pk, p, pinv);
 #pragma unroll
-        for (int i = K + 1; i < M; ++i) {
-            const double l = a[i][K];
-#pragma unroll
-            for (int j = K + 1; j < P; ++j)
-                a[i][j] = submod(mulmod(uk, a[i][j], p, pinv), mulmod(l, a[K][j], p, pinv), p);
-        }
-        int_prefix_steps<M, P, K + 1>(a, u, p, pinv, Pk, D, zero, neg, rel);
+        for (int i = K + 1; i < M; ++i) L[i][K] = x[i];
+        int_left_steps<M, P, K + 1>(L, u, cr, stride, c, p, pinv, Pk, D, zero, neg, rel);
     }
 }
 
@@ -93,8 +115,9 @@ __device__ __forceinline__ void int_prefix_steps(double (&a)[M][P], double (&u)[
 // this lane's `acc`.  `next` is the prefix holding R0 and `rbase` the rank of its
 // first sequence; prefixes [next, pi1) are visited in rounds of up to 64 (one
 // per lane; while their later columns fit the cap projected-column slots);
-// n_prefix = C(n-2, m-2) numbers all prefixes.
-// bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform control flow throughout.
+// n_prefix = C(n-2, m-2) numbers all prefixes.  incl holds 2 x 64 scans (pairs,
+// then projected columns).  bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform
+// control flow outside the lanes' own walks.
 template <int M>
 __device__ void int_prefix_range(const double* cr, int n, const unsigned long long* bt, int bstride,
                                  unsigned long long next, unsigned long long pi1, unsigned long long n_prefix,
@@ -135,46 +158,46 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
         const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);
 
         // ---------------- phase A: the prefix's m-2 fraction-free steps
+        unsigned* cincl = incl + kPrefixBlock;   // projected columns, inclusive scan
+        const unsigned ncols = __shfl(rs, ntake - 1, kWave);
+        double pw0[M], pw1[M];         // the prefix's rows of W, kept for the exchange below
+        unsigned long long prel;       // and its row order
         {
-            double a[M][P];
-#pragma unroll
-            for (int j = 0; j < P; ++j)
-#pragma unroll
-                for (int i = 0; i < M; ++i) a[i][j] = cr[c[j] * ST + i];
+            double L[M][P];
             double u[P];
             unsigned long long rel = 0;
 #pragma unroll
             for (int q = 0; q < M; ++q) rel |= (unsigned long long)q << (4 * q);
             double Pk = 1.0, D = 1.0;
             bool zero = false, neg = false;
-            int_prefix_steps<M, P, 0>(a, u, p, pinv, Pk, D, zero, neg, rel);
+            int_left_steps<M, P, 0>(L, u, cr, ST, c, p, pinv, Pk, D, zero, neg, rel);
             // W rows m-2, m-1 of the elimination operator, by the backward
             // recurrence w <- w E_k (E_k: rows > k scaled by u_k, minus
             // multiples of row k)
-            double w0[M], w1[M];
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                w0[j] = (j == P) ? 1.0 : 0.0;
-                w1[j] = (j == P + 1) ? 1.0 : 0.0;
+                pw0[j] = (j == P) ? 1.0 : 0.0;
+                pw1[j] = (j == P + 1) ? 1.0 : 0.0;
             }
 #pragma unroll
             for (int k = P - 1; k >= 0; --k) {
                 double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                 for (int i = k + 1; i < M; ++i) {
-                    d0 += mulmod(w0[i], a[i][k], p, pinv);
-                    d1 += mulmod(w1[i], a[i][k], p, pinv);
+                    d0 += mulmod(pw0[i], L[i][k], p, pinv);
+                    d1 += mulmod(pw1[i], L[i][k], p, pinv);
                 }
                 d0 = mod_fix(__builtin_fma(-__builtin_floor(d0 * pinv), p, d0), p);
                 d1 = mod_fix(__builtin_fma(-__builtin_floor(d1 * pinv), p, d1), p);
 #pragma unroll
                 for (int j = k + 1; j < M; ++j) {
-                    w0[j] = mulmod(w0[j], u[k], p, pinv);
-                    w1[j] = mulmod(w1[j], u[k], p, pinv);
+                    pw0[j] = mulmod(pw0[j], u[k], p, pinv);
+                    pw1[j] = mulmod(pw1[j], u[k], p, pinv);
                 }
-                w0[k] = submod(w0[k], d0, p);
-                w1[k] = submod(w1[k], d1, p);
+                pw0[k] = submod(pw0[k], d0, p);
+                pw1[k] = submod(pw1[k], d1, p);
             }
+            prel = rel;
             // 1 / D for every prefix of the round: Montgomery's batch inversion
             // over the wave (prefix products, one inverse, suffix products)
             const double Dz = (take && !zero) ? D : 1.0;
@@ -205,9 +228,6 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
             const bool sg = neg ^ ((ps & 1) != 0);
             double F = zero ? 0.0 : inv;
             if (sg && F != 0.0) F = p - F;
-            int off[M];
-#pragma unroll
-            for (int i = 0; i < M; ++i) off[i] = (int)((rel >> (4 * i)) & 15ull);
             const int toff = (int)rs - r;
             if (take) {
                 IntSlot sl;
@@ -218,17 +238,63 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
                 sl.pad = 0;
                 slot[lane] = sl;
                 incl[lane] = ccincl;
+                cincl[lane] = rs;
             }
-            int rmax = take ? r : 0;
+        }
+        wave_lds_sync();
+
+        // ---------------- projection: the round's columns split evenly over the lanes
+        {
+            // runs of an odd number of columns start the lanes on different LDS banks
+            const unsigned per = ((ncols + kWave - 1) / kWave) | 1u;
+            const unsigned g0 = (unsigned)lane * per;
+            const unsigned g1 = min(g0 + per, ncols);
+            // prefix owning column g0: the first s with cincl[s] > g0 (the last
+            // taken prefix for a lane without columns)
+            int s = ntake - 1;
+            if (g0 < ncols) {
+                int l2 = 0, h2 = ntake - 1;
+                while (l2 < h2) {
+                    const int mid = (l2 + h2) >> 1;
+                    if (cincl[mid] > g0) h2 = mid;
+                    else l2 = mid + 1;
+                }
+                s = l2;
+            }
+            unsigned send = cincl[s];
+            double w0[M], w1[M];
+            int off[M];
+            // W of prefix s, from its owner lane (every lane takes part)
+            auto fetch = [&]() {
 #pragma unroll
-            for (int o = kWave / 2; o > 0; o >>= 1) rmax = max(rmax, __shfl_xor(rmax, o, kWave));
-            for (int j = 0; j < rmax; ++j) {
-                const int col = min(c[P - 1] + 1 + j, n - 1);
-                double x[M];
+                for (int i = 0; i < M; ++i) {
+                    w0[i] = __shfl(pw0[i], s, kWave);
+                    w1[i] = __shfl(pw1[i], s, kWave);
+                }
+                const unsigned long long rl = __shfl(prel, s, kWave);
 #pragma unroll
-                for (int i = 0; i < M; ++i) x[i] = cr[col * ST + off[i]];
-                const double t0 = dot_mod<M>(w0, x, p, pinv), t1 = dot_mod<M>(w1, x, p, pinv);
-                if (take && j < r) tv[toff + j] = make_double2(t0, t1);
+                for (int i = 0; i < M; ++i) off[i] = (int)((rl >> (4 * i)) & 15ull);
+            };
+            fetch();
+            for (unsigned it = 0; it < per; ++it) {
+                const unsigned g = g0 + it;
+                const bool act = g < g1;
+                const bool cross = act && g >= send;
+                if (__ballot(cross)) {
+                    if (cross) {
+                        ++s;
+                        send = cincl[s];
+                    }
+                    fetch();
+                }
+                if (act) {
+                    // slot g holds column c_{m-3} + 1 + (g - start of s) = n - send + g
+                    const double* colp = cr + (n - (int)send + (int)g) * ST;
+                    double x[M];
+#pragma unroll
+                    for (int i = 0; i < M; ++i) x[i] = colp[off[i]];
+                    tv[g] = make_double2(dot_mod<M>(w0, x, p, pinv), dot_mod<M>(w1, x, p, pinv));
+                }
             }
         }
         wave_lds_sync();
