@@ -458,7 +458,7 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
 }
 
 template <int M>
-__global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
+__device__ __forceinline__ void batch_int_body(const BatchJob& J) {
     __shared__ IntWaveLds<M> lds[kBatchWaves];
     // binomial table C(x, y), x < kBatchMaxN, y < RADIC_MAX_M, for the prefix walk
     __shared__ unsigned long long bt[M >= 3 && M <= 10 ? kBatchMaxN * RADIC_MAX_M : 1];
@@ -486,6 +486,17 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
         staged = b;
         int_chunk<M>(J, d, mt, c, b, L, bt, lane, restage);
     }
+}
+
+// Up to m = 10 the class is compiled for two waves per SIMD (256 VGPRs; a few
+// bytes spill at m = 10); above, the register need is left to the compiler.
+template <int M>
+__global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_int(BatchJob J) {
+    batch_int_body<M>(J);
+}
+template <int M>
+__global__ __launch_bounds__(kBatchWaves * kWave) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_int_w2(BatchJob J) {
+    batch_int_body<M>(J);
 }
 
 // ---------------------------------------------------------------- finalize (one wave per matrix)
@@ -571,8 +582,13 @@ template <int M>
 static hipError_t launch_int_class(const BatchJob& J, hipStream_t s) {
     static int grid = 0;
     const int block = kBatchWaves * kWave;
-    if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int<M>), block);
-    hipLaunchKernelGGL(k_batch_int<M>, dim3(grid), dim3(block), 0, s, J);
+    if constexpr (M <= 10) {
+        if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int_w2<M>), block);
+        hipLaunchKernelGGL(k_batch_int_w2<M>, dim3(grid), dim3(block), 0, s, J);
+    } else {
+        if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int<M>), block);
+        hipLaunchKernelGGL(k_batch_int<M>, dim3(grid), dim3(block), 0, s, J);
+    }
     return hipGetLastError();
 }
 
