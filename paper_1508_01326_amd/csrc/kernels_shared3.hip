@@ -84,6 +84,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared3(FloatJob J) {
     __shared__ int rowexp[RADIC_MAX_M];
     __shared__ double red[4 * 16];
     __shared__ unsigned long long redn[16];
+    __shared__ unsigned segn[16];   // FP32-bulk: flagged minors per wave
 
     const int n = J.n;
     const int waves = blockDim.x / kWave;
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared3(FloatJob J) {
         }
     }
     if constexpr (F32 && shared_tail_refactor(M)) {
-        shared_fp32_tail<M, 3, kGroupBlock, BS, S64>(J, bt, cd, gcount, gwave, nwaves, nblk, lane, hi, lo, ab, nfb);
+        shared_fp32_tail<M, 3, kGroupBlock, BS, S64>(J, bt, cd, gcount, gwave, nwaves, nblk, segn, hi, lo, ab, nfb);
     } else if (F32 && lane == 0) {
         J.fb_count[gwave] = (unsigned)gcount;   // above J.defer_cap: overflowed
     }

@@ -13,8 +13,8 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kPrefixBlock = 64;     // prefixes of m-2 columns per wave block (prefix-shared kernels)
 constexpr int kGroupBlock = 16;      // prefixes of m-3 columns per wave block (group-shared kernel)
-// FP32-bulk in the shared kernels: up to m = 8 each wave refactors its own
-// flagged minors in double when it is done (an m x m double LU per lane fits the
+// FP32-bulk in the shared kernels: up to m = 8 a workgroup refactors its
+// flagged minors in double when its waves are done (an m x m double LU per lane fits the
 // register budget of three workgroups per compute unit); above, the
 // refactorisation kernel does it.
 __host__ __device__ constexpr bool shared_tail_refactor(int m) { return m <= 8; }

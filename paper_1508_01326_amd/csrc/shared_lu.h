@@ -101,16 +101,22 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
 }
 
 
-// FP32-bulk tail of a prefix-shared wave.  The wave queued its flagged minors in
-// its segment of J.fb_entries (gcount, wave-uniform).  If they fit, its lanes
-// refactor them in double, one per lane, and add them to their sums; otherwise
-// the wave drops its float sums and redoes its own blocks (BLOCK prefixes of
-// m-KT columns: gwave, gwave + nwaves, ...) in double.  Reads the binomial slice
-// bt (stride BS) and the row-scaled double copy cd (column stride S64).
+// FP32-bulk tail of a prefix-shared workgroup.  Each wave queued its flagged
+// minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
+// segment overflowed drops its float sums and redoes its own blocks (BLOCK
+// prefixes of m-KT columns: gwave, gwave + nwaves, ...) in double.  The entries
+// of the other waves are pooled and refactored in double one per thread of the
+// workgroup, in a fixed order (the first threads take them, so one wave's worth
+// of double factorizations serves the whole workgroup).  segn: a workgroup LDS
+// array of 16.  Every thread of the workgroup calls this.  Reads the binomial
+// slice bt (stride BS) and the row-scaled double copy cd (column stride S64).
 template <int M, int KT, int BLOCK, int BS, int S64>
 __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt, const double* cd, int gcount,
                                  unsigned long long gwave, unsigned long long nwaves, unsigned long long nblk,
-                                 int lane, double& hi, double& lo, double& ab, unsigned long long& nfb) {
+                                 unsigned* segn, double& hi, double& lo, double& ab, unsigned long long& nfb) {
+    const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if (lane == 0) segn[wave] = (unsigned)gcount;
+    __syncthreads();
     if (gcount > J.defer_cap) {
         hi = lo = ab = 0.0;
         nfb = 0;
@@ -119,12 +125,23 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
             prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
             redo_ranks_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
         }
-        return;
     }
-    const unsigned* seg = J.fb_entries + (size_t)gwave * J.defer_cap * 4;
-    for (int e = lane; e < gcount; e += kWave) {
+    unsigned E = 0;
+    for (int w = 0; w < waves; ++w)
+        if (segn[w] <= (unsigned)J.defer_cap) E += segn[w];
+    const unsigned long long w0 = (unsigned long long)blockIdx.x * waves;
+    for (unsigned e = threadIdx.x; e < E; e += blockDim.x) {
+        // the segment holding entry e (overflowed segments skipped)
+        int w = 0;
+        unsigned pos = e;
+        for (;; ++w) {
+            const unsigned c = segn[w] <= (unsigned)J.defer_cap ? segn[w] : 0u;
+            if (pos < c) break;
+            pos -= c;
+        }
+        const unsigned* ent = J.fb_entries + ((size_t)(w0 + w) * J.defer_cap + pos) * 4;
         double ad;
-        const double term = refactor_entry_f64<M, S64>(cd, seg + 4 * e, ad);
+        const double term = refactor_entry_f64<M, S64>(cd, ent, ad);
         double sum, err;
         two_sum(hi, term, sum, err);
         hi = sum;
