@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J, int
                     const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
                     for (unsigned long long blk = gw; blk < nblk; blk += nw) {
                         unsigned long long r0, r1;
-                        prefix_block_ranks<M>(J, bt, blk, r0, r1);
+                        prefix_block_ranks<M>(J, bt, prefix_block(J, blk), r0, r1);
                         redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
                     }
                 }
@@ -470,9 +470,7 @@ template <int M, bool F32, bool EXPORT>
 static hipError_t launch_m(const FloatJob& J, int grid, int block, hipStream_t s) {
     constexpr bool DEFER = F32 && !EXPORT;
     const int lds = lds_bytes<M, F32, F32 && !DEFER>(J.n, block / kWave);
-    (void)hipGetLastError();   // clear an error left by an earlier, unrelated call
-    hipLaunchKernelGGL((k_radic_float<M, F32, EXPORT, DEFER>), dim3(grid), dim3(block), lds, s, J);
-    return hipGetLastError();
+    return launch_timed(k_radic_float<M, F32, EXPORT, DEFER>, dim3(grid), dim3(block), lds, s, J);
 }
 
 template <bool F32, bool EXPORT>

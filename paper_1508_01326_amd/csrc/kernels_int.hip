@@ -226,20 +226,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
 }
 
 // ---------------------------------------------------------------- CRT
-// Sum the workgroup residues per prime, then Garner's algorithm (mixed radix
-// digits v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
+// Sum the workgroup residues per prime (every thread takes a strided share;
+// the residues are below 2^31 and there are at most 8192 per prime, so the
+// 64-bit integer sums are exact), then Garner's algorithm (mixed radix digits
+// v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
 // representative in (-P/2, P/2] as sign and 32-bit limbs.
 __global__ __launch_bounds__(256) void k_int_finalize(const double* partials, int grid_x, const IntHeader* h,
                                                       IntResult* out) {
     __shared__ unsigned long long res[RADIC_MAX_PRIMES];
+    __shared__ unsigned long long red[256 / kWave];
     const int k = h->n_primes;
-    for (int t = threadIdx.x; t < k; t += blockDim.x) {
-        const unsigned long long pr = (unsigned long long)g_prime[t];
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, waves = blockDim.x / kWave;
+    for (int t = 0; t < k; ++t) {
         unsigned long long s = 0;
-        for (int b = 0; b < grid_x; ++b) s += (unsigned long long)partials[(long long)t * grid_x + b];
-        res[t] = s % pr;
+        for (int b = threadIdx.x; b < grid_x; b += blockDim.x) s += (unsigned long long)partials[(long long)t * grid_x + b];
+        for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
+        if (lane == 0) red[wave] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long tot = 0;
+            for (int w = 0; w < waves; ++w) tot += red[w];
+            res[t] = tot % (unsigned long long)g_prime[t];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (threadIdx.x != 0) return;
     IntResult r{};
     r.n_primes = k;
@@ -300,16 +310,14 @@ hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned l
     J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
     J.header = reinterpret_cast<IntHeader*>(ws);
     const int lds = int_lds(m, n);
-    (void)hipGetLastError();
     switch (m) {
 #define RADIC_CASE(MM) \
-    case MM: hipLaunchKernelGGL(k_radic_int<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J); break;
+    case MM: return launch_timed(k_radic_int<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J);
         RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
         RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10) RADIC_CASE(11) RADIC_CASE(12)
 #undef RADIC_CASE
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 int int_shared_lds(int m, int n, int waves, int cap) {
@@ -340,22 +348,20 @@ hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned
     J.p_end = n_prefix;
     J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
     const int lds = int_shared_lds(m, n, block / kWave, cap);
-    (void)hipGetLastError();
     switch (m) {
 #define RADIC_CASE(MM) \
-    case MM: hipLaunchKernelGGL(k_radic_int_shared<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J); break;
+    case MM: return launch_timed(k_radic_int_shared<MM>, dim3(grid_x, n_primes), dim3(block), lds, s, J);
         RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6) RADIC_CASE(7) RADIC_CASE(8)
         RADIC_CASE(9) RADIC_CASE(10)
 #undef RADIC_CASE
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s) {
     unsigned char* w = static_cast<unsigned char*>(ws);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_int_finalize, dim3(1), dim3(64), 0, s,
+    hipLaunchKernelGGL(k_int_finalize, dim3(1), dim3(256), 0, s,
                        reinterpret_cast<const double*>(w + int_partials_offset()), grid_x,
                        reinterpret_cast<const IntHeader*>(w), reinterpret_cast<IntResult*>(w + int_result_offset()));
     return hipGetLastError();

@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
 
     for (unsigned long long blk = gwave; blk < nblk && !overflow; blk += nwaves) {
-        unsigned long long next = J.p_begin + blk * kPrefixBlock;
+        unsigned long long next = J.p_begin + prefix_block(J, blk) * kPrefixBlock;
         const unsigned long long pe = next + kPrefixBlock;
         const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
         while (next < pi1 && !overflow) {
@@ -464,9 +464,7 @@ static hipError_t launch_shared_m(const FloatJob& J, int grid, int block, int ld
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    (void)hipGetLastError();
-    hipLaunchKernelGGL((k_radic_shared<M, F32>), dim3(grid), dim3(block), lds, s, J);
-    return hipGetLastError();
+    return launch_timed(k_radic_shared<M, F32>, dim3(grid), dim3(block), lds, s, J);
 }
 
 hipError_t launch_shared(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s) {

@@ -463,9 +463,7 @@ static hipError_t launch_shared3_m(const FloatJob& J, int grid, int block, int l
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
     }
-    (void)hipGetLastError();
-    hipLaunchKernelGGL((k_radic_shared3<M, F32>), dim3(grid), dim3(block), lds, s, J);
-    return hipGetLastError();
+    return launch_timed(k_radic_shared3<M, F32>, dim3(grid), dim3(block), lds, s, J);
 }
 
 hipError_t launch_shared3(int m, int prec, const FloatJob& J, int grid, int block, hipStream_t s) {

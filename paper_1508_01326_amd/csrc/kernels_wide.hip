@@ -146,9 +146,7 @@ __global__ __launch_bounds__(128) void k_radic_wide(FloatJob J, int spl) {
 hipError_t upload_binomials_wide(const unsigned long long* host_table) { return upload_binomial_table(host_table); }
 
 hipError_t launch_wide(const FloatJob& J, int spl, int grid, hipStream_t s) {
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(k_radic_wide, dim3(grid), dim3(128), 0, s, J, spl);
-    return hipGetLastError();
+    return launch_timed(k_radic_wide, dim3(grid), dim3(128), 0, s, J, spl);
 }
 
 }  // namespace radic

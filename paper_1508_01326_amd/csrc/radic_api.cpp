@@ -225,8 +225,10 @@ static hipEvent_t take_event() {
         g_event_pool.pop_back();
         return e;
     }
+    // timing only: without the system-scope fence at the event the kernel
+    // that follows is not held back by a cache write-back
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 
@@ -254,6 +256,115 @@ struct ProfScope {
         a = b = nullptr;
     }
 };
+
+TimedLaunch& timed_launch() {
+    static thread_local TimedLaunch t;
+    return t;
+}
+
+// Times the one main kernel that launch_timed dispatches during its lifetime:
+// the events are bound to that dispatch instead of being recorded around it.
+struct KernelTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    KernelTimer() {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!g_prof) return;
+        a = take_event();
+        b = take_event();
+        if (a && b) timed_launch() = TimedLaunch{a, b, false};
+        else release();
+    }
+    ~KernelTimer() {
+        const bool used = timed_launch().used;
+        timed_launch() = TimedLaunch{};
+        if (!a || !b) return;
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (used) g_prof_events.emplace_back(a, b);
+        else release();
+    }
+    void release() {   // caller holds g_mu
+        if (a) g_event_pool.push_back(a);
+        if (b) g_event_pool.push_back(b);
+        a = b = nullptr;
+    }
+};
+
+// ---------------------------------------------------------------- block order
+// Heaviest-first order of the prefix blocks of a whole-matrix prefix-shared
+// launch.  Block slots go to waves in index order and workgroups are dispatched
+// in index order, so with the heaviest blocks first the last workgroups to start
+// hold light blocks and finish close together (longest processing time first).
+// A block's cost is modelled from the kernel's own round structure: per round
+// (lanes take prefixes while their projected columns fit the cap) a fixed part,
+// a part per column-run of the projection and a part per minor-run of the pair
+// loop, each run being one lane's share of 64.  The weights are cycle estimates
+// of those parts; only their ratios matter.  One table per device and shape
+// (m, n, cap), built and uploaded on the first whole-matrix call and kept until
+// the process ends, so a shape's launches always sum in the same order; a call
+// under stream capture uses a table that already exists, else dictionary order.
+constexpr unsigned long long kOrderMaxBlocks = 1ull << 16;   // 4 Mi prefixes
+static std::map<std::tuple<int, int, int, int>, unsigned*> g_block_order;
+
+static const unsigned* block_order(int m, int n, int cap, unsigned long long n_prefix, hipStream_t stream) {
+    const unsigned long long nblk = (n_prefix + kPrefixBlock - 1) / kPrefixBlock;
+    if (m < 3 || nblk < 2 || nblk > kOrderMaxBlocks) return nullptr;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    const auto key = std::make_tuple(dev, m, n, cap);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_block_order.find(key);
+    if (it != g_block_order.end()) return it->second;
+    // building one allocates: not while the stream is being captured
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+    constexpr double kRound = 13300.0, kColRun = 1600.0, kMinorRun = 530.0;
+    // r = n - 1 - (last prefix column) for every prefix, in dictionary order of
+    // the (m-2)-subsets of the first n-2 columns
+    const int P = m - 2, N = n - 2;
+    std::vector<int> c(P);
+    for (int k = 0; k < P; ++k) c[k] = k;
+    std::vector<double> cost(nblk, 0.0);
+    std::vector<int> rb;
+    rb.reserve(kPrefixBlock);
+    unsigned long long p = 0;
+    for (unsigned long long b = 0; b < nblk; ++b) {
+        rb.clear();
+        for (int l = 0; l < kPrefixBlock && p < n_prefix; ++l, ++p) {
+            rb.push_back(n - 1 - c[P - 1]);
+            int k = P - 1;   // next subset in dictionary order
+            while (k >= 0 && c[k] == N - P + k) --k;
+            if (k >= 0) {
+                ++c[k];
+                for (int j = k + 1; j < P; ++j) c[j] = c[j - 1] + 1;
+            }
+        }
+        size_t i = 0;
+        while (i < rb.size()) {
+            unsigned cols = 0, minors = 0;
+            size_t t = i;
+            while (t < rb.size() && cols + (unsigned)rb[t] <= (unsigned)cap) {
+                cols += (unsigned)rb[t];
+                minors += (unsigned)(rb[t] * (rb[t] - 1) / 2);
+                ++t;
+            }
+            if (t == i) t = i + 1;   // the kernel always takes the first prefix
+            cost[b] += kRound + kColRun * (double)(((cols + kWave - 1) / kWave) | 1u) +
+                       kMinorRun * (double)((minors + kWave - 1) / kWave);
+            i = t;
+        }
+    }
+    std::vector<unsigned> order(nblk);
+    for (unsigned long long b = 0; b < nblk; ++b) order[b] = (unsigned)b;
+    std::stable_sort(order.begin(), order.end(), [&](unsigned x, unsigned y) { return cost[x] > cost[y]; });
+    unsigned* d = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&d), sizeof(unsigned) * nblk) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, order.data(), sizeof(unsigned) * nblk, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return nullptr;
+    }
+    g_block_order.emplace(key, d);
+    return d;
+}
 
 // ---------------------------------------------------------------- validation helpers
 static int check_workspace(void* ws, size_t bytes, size_t need) {
@@ -415,7 +526,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         const int grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
         hipError_t e;
         {
-            ProfScope ps(stream);
+            KernelTimer timer;
             e = launch_wide(J, spl, grid, stream);
         }
         if (e != hipSuccess) return device_error("launch of the wide-minor kernel", e);
@@ -467,6 +578,8 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
             J.mapping = 0;
         } else {
             sh.block = block;
+            if (kt == 2 && J.p_begin == 0 && J.p_end == J.n_prefix)
+                J.block_order = block_order(m, n, J.cap, J.n_prefix, stream);
             const unsigned long long per_block = kt == 2 ? kPrefixBlock : kGroupBlock;
             const unsigned long long blocks = (J.p_end - J.p_begin + per_block - 1) / per_block;
             const unsigned long long wpb = (unsigned long long)(block / kWave);
@@ -478,7 +591,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     J.defer_cap = defer_cap_for(grid, sh.block);
     hipError_t e;
     {
-        ProfScope ps(stream);
+        KernelTimer timer;
         e = !shared ? launch_float(m, prec, false, J, grid, sh.block, stream)
                     : (kt == 2 ? launch_shared(m, prec, J, grid, sh.block, stream)
                                : launch_shared3(m, prec, J, grid, sh.block, stream));
@@ -709,12 +822,12 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
         const unsigned long long wpb = (unsigned long long)(block / kWave);
         unsigned long long g = (blocks + wpb - 1) / wpb;
         grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
-        ProfScope ps(stream);
+        KernelTimer timer;
         e = launch_int_shared(dA, m, n, lda, total, n_prefix, cap, grid, k, block, dWork, stream);
     } else {
         const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
         grid = grid_for(chunks, sh.block);
-        ProfScope ps(stream);
+        KernelTimer timer;
         e = launch_int_main(dA, m, n, lda, total, sh.spl, grid, k, sh.block, dWork, stream);
     }
     if (e != hipSuccess) return device_error("launch of the modular kernel", e);

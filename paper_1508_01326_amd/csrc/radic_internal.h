@@ -1,6 +1,7 @@
 // Internal definitions shared by the HIP translation units of the Radic library.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -70,7 +71,45 @@ struct FloatJob {
     unsigned long long n_prefix;  // C(n-2, m-2) (mapping 1) or C(n-3, m-3) (mapping 2)
     unsigned long long p_begin;   // prefixes [p_begin, p_end) cover [q_begin, q_begin + count)
     unsigned long long p_end;
+    // Mapping 1: the prefix block that the i-th block slot of the launch takes
+    // (heaviest first), or null for blocks in dictionary order.
+    const unsigned* block_order;
 };
+
+// The prefix block behind block slot blk of a launch.
+__device__ __forceinline__ unsigned long long prefix_block(const FloatJob& J, unsigned long long blk) {
+    return J.block_order ? (unsigned long long)J.block_order[blk] : blk;
+}
+
+// ---------------------------------------------------------------- timed launches
+// Start and stop events for the next launch_timed call on this thread: they
+// are bound to that kernel's own dispatch (hipExtLaunchKernel), so timing puts
+// no extra packets on the stream.  Null when launches are not being timed.
+struct TimedLaunch {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+    bool used = false;
+};
+TimedLaunch& timed_launch();
+
+// Launch of a main enumeration kernel: timed by the pending events when there
+// are some, a plain launch otherwise.
+template <typename... Params, typename... Args>
+hipError_t launch_timed(void (*kernel)(Params...), dim3 grid, dim3 block, unsigned lds, hipStream_t s,
+                        Args... args) {
+    static_assert(sizeof...(Params) == sizeof...(Args), "argument count");
+    TimedLaunch& t = timed_launch();
+    (void)hipGetLastError();   // clear an error left by an earlier, unrelated call
+    if (t.start && !t.used) {
+        void* argv[] = {static_cast<void*>(&args)...};
+        const hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, lds, s,
+                                                t.start, t.stop, 0);
+        t.used = e == hipSuccess;
+        return e;
+    }
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------- arithmetic helpers
 __device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {

@@ -122,7 +122,7 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
         nfb = 0;
         for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
             unsigned long long r0, r1;
-            prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
+            prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, prefix_block(J, blk), r0, r1, BS);
             redo_ranks_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
         }
     }
