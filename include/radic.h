@@ -24,6 +24,8 @@
  *    every buffer; the library allocates no device memory per call.  Scratch
  *    space is the caller's workspace (size from radic_workspace_bytes), which
  *    must be 256-byte aligned and must not be shared by calls that may overlap.
+ *    The one device allocation of the library is its own and happens once per
+ *    device and shape: the block-order table of radic_det (see there).
  *  - Matrices are row-major with leading dimension lda >= n (elements).
  *  - Work is enqueued on `stream` (0 = the null stream).  Functions documented
  *    as asynchronous return after enqueueing; their device-side result,
@@ -152,6 +154,11 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch);
  *   dOut   device, one radic_f64_result.
  *   dWork  device workspace of at least radic_workspace_bytes(RADIC_WS_DET, m, n, 0) bytes.
  * Asynchronous.  m > n writes value 0 (Definition 3) and returns RADIC_OK.
+ * The first call for a given device and shape in prefix-shared mode builds a
+ * small table (the order in which waves take blocks of column prefixes, heaviest
+ * first), uploads it synchronously and keeps it until the process ends; later
+ * calls of that shape reuse it, so a shape's results are bitwise reproducible.
+ * A first call made under stream capture skips the table (dictionary order).
  * Errors: EINVAL, ENOTSUP, EOVERFLOW, EWORKSPACE, EDEVICE (nothing enqueued
  * except for EDEVICE).  Non-finite entries give dOut->status = ENONFINITE.
  */
