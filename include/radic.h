@@ -25,7 +25,8 @@
  *    space is the caller's workspace (size from radic_workspace_bytes), which
  *    must be 256-byte aligned and must not be shared by calls that may overlap.
  *    The one device allocation of the library is its own and happens once per
- *    device and shape: the block-order table of radic_det (see there).
+ *    device and shape: the block-order table of radic_det and
+ *    radic_det_int_exact (see radic_det).
  *  - Matrices are row-major with leading dimension lda >= n (elements).
  *  - Work is enqueued on `stream` (0 = the null stream).  Functions documented
  *    as asynchronous return after enqueueing; their device-side result,

@@ -40,7 +40,7 @@ hipError_t upload_binomials_wide(const unsigned long long* host_table);
 hipError_t launch_wide(const FloatJob& J, int spl, int grid, hipStream_t s);
 hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
                              unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
-                             hipStream_t s);
+                             const unsigned* block_order, hipStream_t s);
 size_t int_workspace_bytes();
 hipError_t upload_binomials_batched(const unsigned long long* t);
 hipError_t upload_primes_batched(const unsigned* primes, int count);
@@ -291,7 +291,7 @@ struct KernelTimer {
 
 // ---------------------------------------------------------------- block order
 // Heaviest-first order of the prefix blocks of a whole-matrix prefix-shared
-// launch.  Block slots go to waves in index order and workgroups are dispatched
+// launch (the float kernel and, per prime, the exact one).  Block slots go to waves in index order and workgroups are dispatched
 // in index order, so with the heaviest blocks first the last workgroups to start
 // hold light blocks and finish close together (longest processing time first).
 // A block's cost is modelled from the kernel's own round structure: per round
@@ -822,8 +822,9 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
         const unsigned long long wpb = (unsigned long long)(block / kWave);
         unsigned long long g = (blocks + wpb - 1) / wpb;
         grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
+        const unsigned* order = block_order(m, n, cap, n_prefix, stream);
         KernelTimer timer;
-        e = launch_int_shared(dA, m, n, lda, total, n_prefix, cap, grid, k, block, dWork, stream);
+        e = launch_int_shared(dA, m, n, lda, total, n_prefix, cap, grid, k, block, dWork, order, stream);
     } else {
         const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
         grid = grid_for(chunks, sh.block);
