@@ -227,6 +227,57 @@ __device__ __forceinline__ double refactor_entry_f64(const double* cd, const uns
     return neg ? -d : d;
 }
 
+// Signed term of one queued minor refactored in double by a group of eight
+// lanes (8-aligned in the wave; all eight call together): lane r holds row r of
+// the minor (rows in natural order, from the row-scaled double copy cd), so no
+// register is indexed by a run-time row.  Partial pivoting without exchanges:
+// step k takes the unused row with the largest key |a_rk| (the key of lu_steps,
+// ties to the lower row; the group maximum by three DPP lane moves), broadcasts
+// that row to the group and eliminates the other unused rows with the multipliers
+// and fused multiply-adds of lu_steps.  The permutation's parity is the number
+// of unused rows above each pivot row, summed.  Every lane returns the term.
+template <int M, int ST64 = Layout<M>::st64>
+__device__ __forceinline__ double group_refactor_f64(const double* cd, const unsigned* entry, int lane,
+                                                     double& absdet) {
+    static_assert(M <= 8, "one row per lane of a group of eight");
+    const int r = lane & 7, base = lane & ~7;
+    int c[M];
+    unpack_cols<M>(entry, c);
+    double a[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) a[j] = r < M ? cd[c[j] * ST64 + r] : 0.0;
+    bool used = r >= M;
+    bool zero = false, odd = false;
+    double det = 1.0;
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        unsigned key = used ? 0u : pivot_key(a[k], r);   // an unused row's key is >= 8
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xF, 0xF, false));
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xF, 0xF, false));
+        key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x141, 0xF, 0xF, false));
+        const int p = pivot_row(key);
+        const unsigned gm = (unsigned)(__ballot(!used) >> base) & 0xFFu;
+        odd ^= (__popc(gm & ((1u << p) - 1u)) & 1) != 0;
+        const double piv = __shfl(a[k], base + p, kWave);
+        if (k < M - 1) zero |= (piv == 0.0);
+        det *= piv;
+        const bool elim = !used && r != p;
+        used |= (r == p);
+        if (k < M - 1) {
+            const double l = a[k] * recip(piv);
+#pragma unroll
+            for (int j = k + 1; j < M; ++j) {
+                const double pj = __shfl(a[j], base + p, kWave);
+                const double v = __builtin_fma(-l, pj, a[j]);
+                a[j] = elim ? v : a[j];
+            }
+        }
+    }
+    const double d = zero ? 0.0 : det;
+    absdet = fabs(d);
+    return (radic_sign_odd<M>(c) ^ odd) ? -d : d;
+}
+
 // Refactor queued minors in double, one minor per lane; lane l takes entries
 // l, l + 64, ...  Each lane adds its terms to its own double-double sum.
 template <int M>

@@ -15,9 +15,8 @@ constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) fo
 constexpr int kPrefixBlock = 64;     // prefixes of m-2 columns per wave block (prefix-shared kernels)
 constexpr int kGroupBlock = 16;      // prefixes of m-3 columns per wave block (group-shared kernel)
 // FP32-bulk in the shared kernels: up to m = 8 a workgroup refactors its
-// flagged minors in double when its waves are done (an m x m double LU per lane fits the
-// register budget of three workgroups per compute unit); above, the
-// refactorisation kernel does it.
+// flagged minors in double when its waves are done (eight lanes per minor, one
+// row each); above, the refactorisation kernel does it.
 __host__ __device__ constexpr bool shared_tail_refactor(int m) { return m <= 8; }
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;

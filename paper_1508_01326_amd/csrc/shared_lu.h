@@ -105,9 +105,9 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
 // minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
 // segment overflowed drops its float sums and redoes its own blocks (BLOCK
 // prefixes of m-KT columns: gwave, gwave + nwaves, ...) in double.  The entries
-// of the other waves are pooled and refactored in double one per thread of the
-// workgroup, in a fixed order (the first threads take them, so one wave's worth
-// of double factorizations serves the whole workgroup).  segn: a workgroup LDS
+// of the other waves are pooled and refactored in double by groups of eight
+// threads of the workgroup, in a fixed order (group g takes entries g, g + G, ...;
+// its first lane adds the term).  segn: a workgroup LDS
 // array of 16.  Every thread of the workgroup calls this.  Reads the binomial
 // slice bt (stride BS) and the row-scaled double copy cd (column stride S64).
 template <int M, int KT, int BLOCK, int BS, int S64>
@@ -130,7 +130,9 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
     for (int w = 0; w < waves; ++w)
         if (segn[w] <= (unsigned)J.defer_cap) E += segn[w];
     const unsigned long long w0 = (unsigned long long)blockIdx.x * waves;
-    for (unsigned e = threadIdx.x; e < E; e += blockDim.x) {
+    // eight lanes per entry: group g of the workgroup takes entries g, g + G, ...
+    const unsigned g = threadIdx.x >> 3, G = blockDim.x >> 3;
+    for (unsigned e = g; e < E; e += G) {
         // the segment holding entry e (overflowed segments skipped)
         int w = 0;
         unsigned pos = e;
@@ -141,12 +143,14 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
         }
         const unsigned* ent = J.fb_entries + ((size_t)(w0 + w) * J.defer_cap + pos) * 4;
         double ad;
-        const double term = refactor_entry_f64<M, S64>(cd, ent, ad);
-        double sum, err;
-        two_sum(hi, term, sum, err);
-        hi = sum;
-        lo += err;
-        ab += ad;
+        const double term = group_refactor_f64<M, S64>(cd, ent, lane, ad);
+        if ((lane & 7) == 0) {
+            double sum, err;
+            two_sum(hi, term, sum, err);
+            hi = sum;
+            lo += err;
+            ab += ad;
+        }
     }
 }
 
