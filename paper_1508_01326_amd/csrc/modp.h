@@ -6,19 +6,37 @@
 
 namespace radic {
 
-// Prime set of the exact path (per translation unit, uploaded by the host).
+// Prime set of the exact path (per translation unit, uploaded by the host), and
+// for Garner's recombination the inverse of p_0 p_1 ... p_{i-1} modulo p_i.
 static __device__ double g_prime[RADIC_MAX_PRIMES];
 static __device__ double g_prime_inv[RADIC_MAX_PRIMES];
+static __device__ unsigned long long g_garner_inv[RADIC_MAX_PRIMES];
+
+static inline unsigned long long host_powmod(unsigned long long b, unsigned long long e, unsigned long long p) {
+    unsigned long long r = 1 % p;
+    b %= p;
+    for (; e; e >>= 1) {
+        if (e & 1ull) r = r * b % p;   // operands below 2^31: exact in 64 bits
+        b = b * b % p;
+    }
+    return r;
+}
 
 static inline hipError_t upload_prime_table(const unsigned* primes, int count) {
     double pd[RADIC_MAX_PRIMES] = {0}, pi[RADIC_MAX_PRIMES] = {0};
+    unsigned long long gi[RADIC_MAX_PRIMES] = {0};
     for (int i = 0; i < count && i < RADIC_MAX_PRIMES; ++i) {
         pd[i] = (double)primes[i];
         pi[i] = 1.0 / pd[i];
+        const unsigned long long p = primes[i];
+        unsigned long long prod = 1 % p;
+        for (int j = 0; j < i; ++j) prod = prod * (primes[j] % p) % p;
+        gi[i] = host_powmod(prod, p - 2, p);   // Fermat: the primes are distinct
     }
     hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(g_prime), pd, sizeof(pd));
-    if (e != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(g_prime_inv), pi, sizeof(pi));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_prime_inv), pi, sizeof(pi));
+    if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(g_garner_inv), gi, sizeof(gi));
+    return e;
 }
 
 template <int M> struct IntLayout {
@@ -119,18 +137,8 @@ __device__ __forceinline__ void frac_add(double& n1, double& d1, double n2, doub
     d1 = mulmod(d1, d2, p, pinv);
 }
 
-__device__ unsigned long long powmod_u64(unsigned long long b, unsigned long long e, unsigned long long p) {
-    unsigned long long r = 1 % p;
-    b %= p;
-    while (e) {
-        if (e & 1ull) r = (r * b) % p;
-        b = (b * b) % p;
-        e >>= 1;
-    }
-    return r;
-}
-
-// Chinese remaindering of residues res[i] mod pr[i] (distinct odd primes),
+// Chinese remaindering of residues res[i] mod pr[i] (the first k primes of the
+// uploaded set, whose Garner inverses are in g_garner_inv),
 // Garner's mixed-radix form: S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ..., then the
 // representative in (-P/2, P/2], P = prod p_i, written as sign (-1, 0, 1) and
 // little-endian 32-bit limbs mag[0..len-1] (mag holds at least k + 1 limbs).
@@ -138,12 +146,12 @@ __device__ inline void crt_to_limbs(const unsigned long long* res, const unsigne
                                     int& len_out, unsigned* mag) {
     unsigned long long v[RADIC_MAX_PRIMES];
     for (int i = 0; i < k; ++i) {
-        // value of the digits found so far, and the product of the earlier primes, mod p_i
-        unsigned long long t = 0, prod = 1 % pr[i];
+        // value of the digits found so far mod p_i, times the uploaded inverse of
+        // the product of the earlier primes (pr is the uploaded prime set)
+        unsigned long long t = 0;
         for (int j = i - 1; j >= 0; --j) t = (t * (pr[j] % pr[i]) + v[j]) % pr[i];
-        for (int j = 0; j < i; ++j) prod = (prod * (pr[j] % pr[i])) % pr[i];
         const unsigned long long diff = (res[i] % pr[i] + pr[i] - t) % pr[i];
-        v[i] = i == 0 ? res[0] % pr[0] : (diff * powmod_u64(prod, pr[i] - 2, pr[i])) % pr[i];
+        v[i] = i == 0 ? res[0] % pr[0] : (diff * g_garner_inv[i]) % pr[i];
     }
     // S = v_{k-1}; S = S * p_i + v_i (Horner, 32-bit limbs); P = prod p_i
     unsigned S[RADIC_MAX_PRIMES + 1] = {0}, Pm[RADIC_MAX_PRIMES + 1] = {0};
