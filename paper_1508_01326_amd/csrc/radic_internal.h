@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <tuple>
+
 #include "radic.h"
 
 namespace radic {
@@ -100,7 +102,13 @@ hipError_t launch_timed(void (*kernel)(Params...), dim3 grid, dim3 block, unsign
     TimedLaunch& t = timed_launch();
     (void)hipGetLastError();   // clear an error left by an earlier, unrelated call
     if (t.start && !t.used) {
-        void* argv[] = {static_cast<void*>(&args)...};
+        // the arguments converted to the kernel's own parameter types
+        std::tuple<Params...> held(args...);
+        void* argv[sizeof...(Params)];
+        std::apply([&argv](auto&... a) {
+            int i = 0;
+            ((argv[i++] = static_cast<void*>(&a)), ...);
+        }, held);
         const hipError_t e = hipExtLaunchKernel(reinterpret_cast<const void*>(kernel), grid, block, argv, lds, s,
                                                 t.start, t.stop, 0);
         t.used = e == hipSuccess;
