@@ -22,6 +22,7 @@ import os
 import sys
 import time
 
+TIME_EVERY = 4   # timed steps whose dominant kernel the library times with events: 1 in TIME_EVERY
 METRIC = "Radic subdeterminants/sec, m=8 n=32: FP64 vs FP32-bulk at stated error"
 UNIT = "subdeterminants/s"
 PEAK_FP64_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, one FP64 FMA per lane per clock
@@ -182,8 +183,8 @@ def kernel_name(enumeration, form):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared", "group_shared"],
                     help="enumeration used by the library (default: auto, prefix-shared where supported)")
@@ -258,20 +259,23 @@ def main():
     if len(warm) >= 2:
         dom = "fp64" if sum(warm[0::2]) >= sum(warm[1::2]) else "fp32_bulk"
 
-    def timed_step():
-        # inside the timed region the library times the dominant kernel only
-        # (with events bound to its dispatch): every timed launch costs the
-        # stream a few microseconds
+    def timed_step(i):
+        # inside the timed region the library times the dominant kernel (with
+        # events bound to its dispatch) on every TIME_EVERY-th step: a timed
+        # launch lengthens its step by about 13 us (0.164 against 0.151 ms per
+        # step untimed), so timing every launch would slow the steps measured
         for p in ("fp64", "fp32_bulk"):
-            if dom is None or p == dom:
+            on = (dom is None or p == dom) and i % TIME_EVERY == 0
+            if on:
                 radic.profile_enable(True)
             radic.radic_det(A, precision=p, out=outs[p], work=work[p], sync=False)
-            radic.profile_enable(False)
+            if on:
+                radic.profile_enable(False)
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        timed_step()
+    for i in range(args.steps):
+        timed_step(i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     timed = radic.profile_read_launches()
@@ -357,7 +361,8 @@ def main():
                                  f"{xflop / total:.2f} FLOP per minor (averaged over the launch; "
                                  f"{args.enumeration} enumeration), {xflop:.4g} FLOP, "
                                  f"{xflop / (dom_ms * 1e-3) / 1e12:.2f} TFLOP/s",
-                     "kernel_ms": dom_ms, "launches_timed": len(timed)},
+                     "kernel_ms": dom_ms, "launches_timed": len(timed),
+                     "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},
         "cpu_baseline": cpu,
         "forms": per_form,
     }

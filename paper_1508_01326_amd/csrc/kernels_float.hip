@@ -418,7 +418,7 @@ __device__ __forceinline__ void add_partials(const Partial* parts, int G, double
     }
 }
 
-__global__ __launch_bounds__(1024) void k_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2,
+__global__ __launch_bounds__(512) void k_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2,
                                                          const DetHeader* h, radic_f64_result* out,
                                                          unsigned long long count, int use_scale) {
     __shared__ double red[4 * 16];
@@ -540,7 +540,7 @@ hipError_t launch_float(int m, int prec, bool export_terms, const FloatJob& J, i
 hipError_t launch_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2, const DetHeader* h,
                                  radic_f64_result* out, unsigned long long count, int use_scale, hipStream_t s) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(1024), 0, s, parts, G, fb_parts, G2, h, out, count,
+    hipLaunchKernelGGL(k_finalize_float, dim3(1), dim3(512), 0, s, parts, G, fb_parts, G2, h, out, count,
                        use_scale);
     return hipGetLastError();
 }
