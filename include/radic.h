@@ -310,8 +310,12 @@ int radic_set_fallback_tau(double tau);
 int radic_set_enumeration(int mode);
 
 /*
- * Timing hook for benchmarks: while enabled, the library records HIP events on
- * the launch stream around every launch of its main enumeration kernels.
+ * Timing hook for benchmarks: while enabled, the library times every launch of
+ * its main enumeration kernels with HIP events on the launch stream.  For the
+ * single-matrix float and exact calls the events are bound to the kernel's own
+ * dispatch (hipExtLaunchKernel; created without the system-scope fence); for
+ * the two-row, batched and graph calls they are recorded around the launches.
+ * A timed launch still delays the stream by a few microseconds.
  * radic_profile_read waits for them and returns the summed duration in ms and
  * the number of launches since the last read, then clears.
  */
