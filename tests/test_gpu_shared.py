@@ -177,6 +177,20 @@ def test_fallback_forced_everywhere():
     assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-12, "all fallback")
 
 
+@pytest.mark.parametrize("m", [3, 4, 5, 6, 7, 8])
+def test_fallback_forced_each_m(m):
+    # every minor refactored in double by the workgroup's tail, for each m it
+    # serves (eight lanes per minor, rows beyond m idle)
+    n = m + 7
+    A = workloads.random_float(m, n, seed=900 + m)
+    ref = oracle.radic_f64(A)
+    radic.set_fallback_tau(float("inf"))
+    got = run(A, "fp32_bulk", f"tau=inf m={m}")
+    assert got["n_fallback"] == math.comb(n, m)
+    assert_close(got["value"], ref["value"], ref["abs_sum"], 1e-12, f"all fallback m={m}")
+    assert_close(got["abs_sum"], ref["abs_sum"], ref["abs_sum"], 1e-12, "abs_sum")
+
+
 def test_fallback_near_parallel_columns():
     rng = np.random.default_rng(89)
     A = rng.standard_normal((6, 20))
