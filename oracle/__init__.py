@@ -23,7 +23,7 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_build.LIB):
+        if _build.stale():
             _build.build()
         L = ctypes.CDLL(_build.LIB)
         u64, i64, i32 = ctypes.c_uint64, ctypes.c_int64, ctypes.c_int
@@ -42,6 +42,8 @@ def lib():
         L.oracle_successor.restype = i32
         L.oracle_subset_term_f64.argtypes = [dp, i32, i32, i64, u64, ip]
         L.oracle_subset_term_f64.restype = ctypes.c_double
+        L.oracle_subset_terms_f64.argtypes = [dp, i32, i32, i64, u64, u64, dp]
+        L.oracle_subset_terms_f64.restype = i32
         L.oracle_radic_f64_range.argtypes = [dp, i32, i32, i64, u64, u64, i32, dp]
         L.oracle_radic_f64_range.restype = i32
         L.oracle_radic_int_range.argtypes = [i32p, i32, i32, i64, u64, u64, i32, u32p, i32, ip, ip]
@@ -132,6 +134,23 @@ def subset_term_f64(A, q):
     B = (ctypes.c_int * m)()
     v = lib().oracle_subset_term_f64(A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m, n, n, q, B)
     return v, list(B)
+
+
+def subset_terms_f64(A, q0=0, count=None):
+    """The signed FP64 terms (-1)^(r+s) det(A_J) of ranks [q0, q0 + count) in rank
+    order (count None: to the end), as a numpy array; the same values the
+    summing enumerator adds."""
+    A = _as_f64(A)
+    m, n = A.shape
+    total = binomial(n, m)
+    if count is None:
+        count = total - q0
+    out = np.empty(int(count), dtype=np.float64)
+    rc = lib().oracle_subset_terms_f64(A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), m, n, n, q0, count,
+                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    if rc != 0:
+        raise ValueError(f"oracle_subset_terms_f64 failed with {rc}")
+    return out
 
 
 def _limbs_to_int(mag, length, sign):

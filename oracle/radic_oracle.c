@@ -201,6 +201,29 @@ double oracle_subset_term_f64(const double *A, int m, int n, int64_t lda, uint64
     return radic_sign(B, m) * det_gepp(M, m);
 }
 
+/* The signed terms (-1)^(r+s) det(A_J) of ranks q0 .. q0+count-1, in rank order,
+ * each computed exactly as the summing loop below computes it (one thread, the
+ * successor of Section 5 between ranks).  Lets a test check the compensated sum
+ * against a correctly rounded sum of the very same terms.  Returns 0, or -1 for
+ * bad arguments / a range past the end. */
+int oracle_subset_terms_f64(const double *A, int m, int n, int64_t lda, uint64_t q0, uint64_t count, double *out)
+{
+    if (m < 1 || n < m || m > ORACLE_MAX_M || lda < n) return -1;
+    int ovf = 0;
+    uint64_t total = binom_u64(n, m, &ovf);
+    if (ovf || q0 > total || count > total - q0) return -1;
+    int B[ORACLE_MAX_M];
+    double M[ORACLE_MAX_M * ORACLE_MAX_M];
+    if (count == 0) return 0;
+    oracle_unrank(q0, m, n, B);
+    for (uint64_t t = 0; t < count; ++t) {
+        gather_f64(A, lda, m, B, M);
+        out[t] = radic_sign(B, m) * det_gepp(M, m);
+        if (t + 1 < count) oracle_successor(B, m, n);
+    }
+    return 0;
+}
+
 typedef struct {
     const double *A;
     int64_t lda;
