@@ -92,9 +92,25 @@ def executed_flops(m, n, enumeration):
     return flops
 
 
+def host_info():
+    """Host CPU: logical cores the process may use and the model name."""
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return nproc, model
+
+
 def cpu_baseline(A, threads, max_seconds=20.0):
-    """The oracle (FP64 GEPP enumeration) timed on the host: the whole workload,
-    repeated while under the time budget; median rate."""
+    """The oracle (FP64 GEPP enumeration, compensated sum) timed on the host: the
+    whole workload on `threads` threads, repeated while under the time budget
+    (median rate), then once on one thread."""
     import oracle
     m, n = A.shape
     total = math.comb(n, m)
@@ -109,61 +125,184 @@ def cpu_baseline(A, threads, max_seconds=20.0):
         if time.perf_counter() - t_start > max_seconds:
             break
     rates.sort()
-    return rates[len(rates) // 2], values[0], len(rates)
+    t0 = time.perf_counter()
+    oracle.radic_f64(A, nthreads=1)
+    rate1 = total / (time.perf_counter() - t0)
+    return rates[len(rates) // 2], values[0], len(rates), rate1
+
+
+def read_golden(name):
+    """Stored expected values written by tests/golden/make_golden.py (oracle only)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", name)
+    rows = []
+    with open(path) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                rows.append(line.split())
+    return rows
+
+
+def timed_calls(fn, steps, torch):
+    """Mean wall time of `steps` calls of fn() (each waits for its result), ms."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def kernel_ms(radic, fn, reps):
+    """Mean duration of the main enumeration kernel of fn() (library timing hook)."""
+    radic.profile_read_launches()
+    radic.profile_enable(True)
+    for _ in range(reps):
+        fn()
+    radic.profile_enable(False)
+    ms = radic.profile_read_launches()
+    return sum(ms) / len(ms) if ms else None
 
 
 def other_workloads(radic, binding, workloads, torch, dev, args):
-    """Secondary figures (not the headline): the exact-integer 6x40 workload and
-    the batched 4096-matrix workload, each timed with events around K calls
-    after warm-up, checked against the oracle (exact) or sampled oracle values."""
+    """The other configurations, each checked against the oracle or the stored
+    oracle values: the 5x14 latency case, the exact 6x40 int32 matrix, the 12x36
+    precision stress in both precisions and the 4096-matrix batch."""
     import numpy as np
-    import oracle
+    from fractions import Fraction
+    from oracle import exact
     out = {}
-    # exact integer path: synchronous per call (the result comes back to the host)
+
+    # 5 x 14, 2002 minors: end-to-end latency of one call through the C ABI
+    # (enqueue, kernels, wait, copy of the 56-byte result to the host)
+    A = workloads.single_matrix(1)
+    dA = torch.from_numpy(A).to(dev)
+    ex = float(exact.radic_subset_dp(A))
+    res = {}
+    for p in ("fp64", "fp32_bulk"):
+        o = binding.new_f64_result(dev)
+        w = binding.workspace(radic.RADIC_WS_DET, 5, 14, device=dev)
+        call = lambda: radic.radic_det(dA, precision=p, out=o, work=w)   # noqa: E731
+        for _ in range(10):
+            r = call()
+        ms = timed_calls(call, 200, torch)
+        S = r["abs_sum"]
+        res[p] = {"latency_us": ms * 1e3, "err_over_sum_abs_vs_exact": abs(r["value"] - ex) / S,
+                  "kernel_us": kernel_ms(radic, call, 20) * 1e3}
+    out["w1_5x14"] = {"minors": 2002, "forms": res,
+                      "note": "latency = one synchronous call incl. result copy to host, mean of 200"}
+
+    # 6 x 40 int32, exact: synchronous call (two small read-backs)
     A = workloads.single_matrix(3)
     m, n = A.shape
     total = math.comb(n, m)
     dA = torch.from_numpy(A).to(dev)
     work = binding.workspace(radic.RADIC_WS_INT, m, n, device=dev)
-    for _ in range(max(1, args.warmup)):
-        got = radic.radic_det_int_exact(dA, work=work)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        got = radic.radic_det_int_exact(dA, work=work)
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    out["exact_int_6x40"] = {"minors": total, "ms_per_call": ms, "subdet_per_s": total / (ms * 1e-3),
-                             "bit_exact_vs_oracle": got == oracle.radic_int(A),
-                             "note": "host-synchronous call including the 2 x 4-byte result copy"}
-    # batched: one graph launch over the 4096 matrices
-    mats = [M for _, M in workloads.batch_matrices()]
+    call = lambda: radic.radic_det_int_exact(dA, work=work)   # noqa: E731
+    for _ in range(5):
+        got = call()
+    ms = timed_calls(call, 50, torch)
+    kms = kernel_ms(radic, call, 10)
+    out["w3_6x40_exact"] = {"minors": total, "ms_per_call": ms, "subdet_per_s": total / (ms * 1e-3),
+                            "kernel": "k_radic_int_shared<6>", "kernel_ms": kms, "primes": 2,
+                            "minor_primes_per_s_kernel": 2 * total / (kms * 1e-3),
+                            "bit_exact_vs_oracle": got == exact.radic_subset_dp(A)}
+
+    # 12 x 36 precision stress: 1,251,677,700 minors per form
+    A = workloads.single_matrix(4)
+    g = {r[0]: r[1] for r in read_golden("workload4_12x36.txt")}
+    ex = float(Fraction(int(g["exact_num"]), int(g["exact_den"])))
+    S = float(g["oracle_abs_sum"])
+    total = math.comb(36, 12)
+    dA = torch.from_numpy(A).to(dev)
+    res = {}
+    for p in ("fp64", "fp32_bulk"):
+        o = binding.new_f64_result(dev)
+        w = binding.workspace(radic.RADIC_WS_DET, 12, 36, device=dev)
+        call = lambda: radic.radic_det(dA, precision=p, out=o, work=w)   # noqa: E731
+        r = call()
+        ms = timed_calls(call, 3, torch)
+        kms = kernel_ms(radic, call, 2)
+        enum = "per_minor" if p == "fp64" else "auto"      # FP64 prefix sharing stops at m = 10
+        xf = executed_flops(12, 36, enum)
+        peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
+        res[p] = {"ms_per_call": ms, "subdet_per_s": total / (ms * 1e-3),
+                  "err_over_sum_abs_vs_exact": abs(r["value"] - ex) / S, "tol": 1e-12 if p == "fp64" else 1e-5,
+                  "n_fallback": r["n_fallback"], "fallback_fraction": r["n_fallback"] / total,
+                  "kernel": ("k_radic_float<12,false,false,false>" if p == "fp64" else "k_radic_shared<12,true>"),
+                  "kernel_ms": kms,
+                  "roofline": {"bound": "alu", "achieved": xf / (kms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                               "frac": xf / (kms * 1e-3) / 1e12 / peak,
+                               "per_unit": f"executed {xf / total:.1f} FLOP per minor ({enum} enumeration)"}}
+    out["w4_12x36"] = {"minors": total, "forms": res}
+
+    # 4096 matrices in one HIP-graph launch, every result against the stored values
+    batch_list = workloads.batch_matrices()
+    mats = [M for _, M in batch_list]
+    gold = read_golden("workload5_batch4096.txt")
     batch = radic.Batch(mats, device=dev)
-    g = radic.BatchGraph(batch, precision="fp32_bulk")
-    for _ in range(max(1, args.warmup)):
-        g.launch()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(args.steps):
-        g.launch()
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
-    res = batch.results()
-    minors = sum(math.comb(M.shape[1], M.shape[0]) for M in mats)
-    bad = 0
-    for b in range(0, len(mats), 97):                 # sampled check against the oracle
-        M = mats[b]
-        if M.dtype == np.int32:
-            bad += res[b]["exact"] != oracle.radic_int(M)
-        else:
-            ref = oracle.radic_f64(M)
-            bad += abs(res[b]["value"] - ref["value"]) > 1e-5 * max(ref["abs_sum"], 1e-300)
-    out["batched_4096"] = {"minors": minors, "ms_per_launch": ms, "subdet_per_s": minors / (ms * 1e-3),
-                           "float_precision": "fp32_bulk", "sampled_mismatches": int(bad),
-                           "note": "one HIP-graph replay per launch; ints exact, floats FP32-bulk"}
+    res = {}
+    for p in ("fp32_bulk", "fp64"):
+        gph = radic.BatchGraph(batch, precision=p)
+        for _ in range(3):
+            gph.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 10
+        e0.record()
+        for _ in range(reps):
+            gph.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        rr = batch.results()
+        gph.destroy()
+        bad = 0
+        tol = 1e-12 if p == "fp64" else 1e-5
+        for b, (kind, M) in enumerate(batch_list):
+            gr = gold[b]
+            if rr[b]["status"] != 0:
+                bad += 1
+            elif kind == "i32":
+                bad += rr[b]["exact"] != int(gr[4])
+            else:
+                Sg = float(gr[5])
+                if Sg <= 1e-9 * exact.hadamard_sum(M):
+                    Sg = exact.hadamard_sum(M)
+                bad += not abs(rr[b]["value"] - float(gr[4])) <= tol * Sg
+        minors = sum(r["n_subsets"] for r in rr)
+        res[p] = {"ms_per_launch": ms, "subdet_per_s": minors / (ms * 1e-3), "mismatches_vs_oracle": int(bad),
+                  "checked": len(batch_list)}
+    out["w5_batch4096"] = {"minors": 342865835, "float_forms": res,
+                           "note": "one HIP-graph replay per launch; int32 matrices exact (bit-exact check), "
+                                   "float64 matrices in the named precision"}
     return out
+
+
+def per_minor_roofline(radic, A, outs, work, torch):
+    """The per-minor kernels (every minor unranked or advanced and factored on
+    its own, Sections 4-6) on the same matrix, on the counted (2/3) m^3 FLOP per
+    minor, outside the timed steps."""
+    m, n = A.shape
+    total = math.comb(n, m)
+    radic.set_enumeration("per_minor")
+    res = {}
+    try:
+        for p, peak in (("fp64", PEAK_FP64_TFLOPS), ("fp32_bulk", PEAK_FP32_TFLOPS)):
+            call = lambda: radic.radic_det(A, precision=p, out=outs[p], work=work[p], sync=False)   # noqa: E731
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            kms = kernel_ms(radic, call, 10)
+            torch.cuda.synchronize()
+            flop = counted_flops_per_minor(m) * total
+            res[p] = {"kernel": kernel_name("per_minor", p), "bound": "alu", "kernel_ms": kms,
+                      "achieved": flop / (kms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
+                      "frac": flop / (kms * 1e-3) / 1e12 / peak,
+                      "per_unit": f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} FLOP per minor x {total} "
+                                  f"minors (executed {executed_flops(m, n, 'per_minor') / total:.0f})"}
+    finally:
+        radic.set_enumeration("auto")
+    return res
 
 
 def traffic_for(form, enumeration):
@@ -188,9 +327,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--enumeration", default="auto", choices=["auto", "per_minor", "prefix_shared", "group_shared"],
                     help="enumeration used by the library (default: auto, prefix-shared where supported)")
-    ap.add_argument("--other", action="store_true",
-                    help="also time the exact-integer workload (6x40 int32) and the batched workload "
-                         "(4096 mixed matrices, one HIP-graph launch); reported under other_workloads")
+    ap.add_argument("--no-other", action="store_true",
+                    help="skip the other workloads (5x14 latency, exact 6x40 int32, 12x36 precision stress, "
+                         "4096-matrix batch) and the per-minor kernels' roofline")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="before the steps, run one plain device-to-device copy of this many bytes (a "
                          "known-size reference for the HBM byte counters of a profiler run)")
@@ -303,13 +442,15 @@ def main():
     res = {p: binding.read_f64_result(outs[p]) for p in outs}
 
     # CPU oracle: baseline rate and the reference value for the error figures
-    threads = min(os.cpu_count() or 1, 16)
+    nproc, cpu_model = host_info()
+    threads = min(nproc or 1, 16)
     cpu = None
     if not args.no_cpu:
-        rate, ref, reps = cpu_baseline(A_host, threads)
+        rate, ref, reps, rate1 = cpu_baseline(A_host, threads)
         cpu = {"value": rate, "unit": UNIT, "cores": threads, "kind": "oracle",
                "sample": f"whole workload (all {total} minors, FP64 GEPP + compensated sum), "
-                         f"median of {reps} run(s) on {threads} threads"}
+                         f"median of {reps} run(s) on {threads} threads; once more on 1 thread",
+               "value_1_thread": rate1, "host_nproc": nproc, "host_cpu": cpu_model}
     else:
         import oracle
         ref = oracle.radic_f64(A_host, nthreads=threads)
@@ -332,9 +473,11 @@ def main():
             "kernel_counted_tflops": flop / (avg * 1e-3) / 1e12,
             "peak_tflops": peak,
         }
-    # algorithmic work: the counted (2/3) m^3 FLOP of one minor's elimination;
-    # the prefix-shared kernels execute far fewer, stated beside it
-    achieved = flop / (dom_ms * 1e-3) / 1e12
+    # roofline of the dominant kernel on the floating-point operations it
+    # executes (prefix sharing removes most of the counted (2/3) m^3 per minor:
+    # a different method, so the counted figure is reported beside it, labelled)
+    achieved = xflop / (dom_ms * 1e-3) / 1e12
+    counted = flop / (dom_ms * 1e-3) / 1e12
     peak = per_form[dom]["peak_tflops"]
     line = {
         "metric": METRIC,
@@ -356,17 +499,21 @@ def main():
         "roofline": {"bound": "alu", "kernel": kernel_name(args.enumeration, dom),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": traffic_for(dom, args.enumeration),
-                     "per_unit": f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} FLOP per minor x {total} "
-                                 f"minors per launch = {flop:.4g} FLOP; the kernel executes "
-                                 f"{xflop / total:.2f} FLOP per minor (averaged over the launch; "
-                                 f"{args.enumeration} enumeration), {xflop:.4g} FLOP, "
-                                 f"{xflop / (dom_ms * 1e-3) / 1e12:.2f} TFLOP/s",
+                     "per_unit": f"executed {xflop / total:.2f} FLOP per minor (averaged over the launch; "
+                                 f"{args.enumeration} enumeration) x {total} minors = {xflop:.4g} FLOP per launch",
+                     "counted_equivalent": {"tflops": counted, "frac": counted / peak,
+                                            "per_unit": f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} "
+                                                        f"FLOP per minor x {total} minors = {flop:.4g} FLOP, "
+                                                        f"a different method's work"},
                      "kernel_ms": dom_ms, "launches_timed": len(timed),
                      "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},
         "cpu_baseline": cpu,
         "forms": per_form,
     }
-    if args.other:
+    if not args.no_other:
+        print("[bench] per-minor kernels", file=sys.stderr, flush=True)
+        line["roofline_per_minor"] = per_minor_roofline(radic, A, outs, work, torch)
+        print("[bench] other workloads", file=sys.stderr, flush=True)
         line["other_workloads"] = other_workloads(radic, binding, workloads, torch, dev, args)
     for p in per_form:
         if per_form[p]["err_over_sum_abs"] > per_form[p]["tol"]:

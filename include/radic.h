@@ -24,9 +24,11 @@
  *    every buffer; the library allocates no device memory per call.  Scratch
  *    space is the caller's workspace (size from radic_workspace_bytes), which
  *    must be 256-byte aligned and must not be shared by calls that may overlap.
- *    The one device allocation of the library is its own and happens once per
- *    device and shape: the block-order table of radic_det and
- *    radic_det_int_exact (see radic_det).
+ *    The first call on a device (any entry point) uploads the library's
+ *    constant tables (binomial coefficients, primes) synchronously; make it
+ *    outside stream capture.  After that, radic_det, radic_det_range and
+ *    radic_det_batched allocate nothing, never synchronise with the host and
+ *    can be captured into a HIP graph.
  *  - Matrices are row-major with leading dimension lda >= n (elements).
  *  - Work is enqueued on `stream` (0 = the null stream).  Functions documented
  *    as asynchronous return after enqueueing; their device-side result,
@@ -72,7 +74,10 @@ typedef enum {
     RADIC_FP64 = 0,      /* every minor factored in IEEE double */
     RADIC_FP32_BULK = 1  /* minors factored in float on rows pre-scaled by exact powers of two;
                             minors whose product of capped pivot ratios falls below tau are
-                            refactored in double; all accumulation in double */
+                            refactored in double; all accumulation in double.  A call (or a
+                            batch matrix) over fewer than 4096 minors refactors every minor
+                            in double (n_fallback = its minor count): only a sum over many
+                            minors absorbs the float error within the tolerance */
 } radic_precision;
 
 /* Workspace kinds for radic_workspace_bytes. */
@@ -142,7 +147,11 @@ const char *radic_last_error(void);
 int radic_version(void);
 
 /* Bytes of device workspace needed by one call of the given kind.
- * RADIC_WS_DET / RADIC_WS_INT: for an m x n matrix (batch ignored).
+ * RADIC_WS_DET / RADIC_WS_INT: for an m x n matrix (batch ignored).  The
+ * RADIC_WS_DET size grows with C(n, m): it holds the FP32-bulk queue of minors
+ * awaiting a double refactorisation, 16 bytes per 64 minors, between 64 MiB
+ * and 512 MiB (about 68 MiB for 8 x 32, 313 MiB for 12 x 36).  A larger
+ * workspace than asked for gives the queue more room.
  * RADIC_WS_BATCHED: for `batch` matrices (m, n ignored).
  * Returns 0 for invalid arguments. */
 size_t radic_workspace_bytes(int kind, int m, int n, int batch);
@@ -155,11 +164,10 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch);
  *   dOut   device, one radic_f64_result.
  *   dWork  device workspace of at least radic_workspace_bytes(RADIC_WS_DET, m, n, 0) bytes.
  * Asynchronous.  m > n writes value 0 (Definition 3) and returns RADIC_OK.
- * The first call for a given device and shape in prefix-shared mode builds a
- * small table (the order in which waves take blocks of column prefixes, heaviest
- * first), uploads it synchronously and keeps it until the process ends; later
- * calls of that shape reuse it, so a shape's results are bitwise reproducible.
- * A first call made under stream capture skips the table (dictionary order).
+ * The minors are summed in an order fixed by the shape and the launch shape
+ * (in prefix-shared mode, blocks of column prefixes taken in colex order,
+ * heaviest first), so repeated calls, eager or replayed from a captured graph,
+ * give the same bits.
  * Errors: EINVAL, ENOTSUP, EOVERFLOW, EWORKSPACE, EDEVICE (nothing enqueued
  * except for EDEVICE).  Non-finite entries give dOut->status = ENONFINITE.
  */
@@ -208,11 +216,15 @@ int radic_det_2xn(const double *dA, int64_t n, int64_t lda, radic_f64_result *dO
                   size_t work_bytes, hipStream_t stream);
 
 /*
- * radic_det_int_exact -- exact Radic determinant of one int32 matrix.
- * Each minor is eliminated fraction-free modulo k 31-bit primes (k chosen on the
- * device from a Hadamard-type bound so that the product of the primes exceeds
- * twice the largest possible |result|), residues are summed per prime and
- * combined by Garner's mixed-radix CRT into a signed integer.
+ * radic_det_int_exact -- exact Radic determinant of one int32 matrix: the sum of
+ * Definition 3, eq. (1) over all C(n, m) column sequences of Sections 3-5, as an
+ * exact integer.  (The multi-modular evaluation is this library's, not the
+ * paper's.)  Each minor is eliminated fraction-free modulo k 31-bit primes (k
+ * chosen on the device from a Hadamard-type bound so that the product of the
+ * primes exceeds twice the largest possible |result|), residues are summed per
+ * prime and combined by Garner's mixed-radix CRT into a signed integer.
+ *   dA         device, m x n int32, row-major, leading dimension lda (elements).
+ *   dWork      device workspace of at least radic_workspace_bytes(RADIC_WS_INT, m, n, 0).
  *   hMag       host, capacity mag_capacity little-endian 32-bit limbs of |result|.
  *   hMagLen    host, number of significant limbs written (0 for a zero result);
  *              on RADIC_EOVERFLOW the number of limbs needed.
@@ -339,6 +351,14 @@ int radic_set_prime_set(const uint32_t *hPrimes, int count);
 int radic_host_binomial(int a, int b, uint64_t *hOut);
 int radic_host_unrank(int m, int n, uint64_t q, int *hCols);
 int radic_host_prime(int i, uint32_t *hPrime);
+/* How radic_det_batched cuts the rank space of one matrix (dtype 0 float64,
+ * 1 int32) into chunks, the unit a wave takes from its class queue (the
+ * granularity scheme of Section 5): *hChunk ranks per chunk (a multiple of 64,
+ * at least 64 * subsets_per_lane), *hChunks chunks.  Float matrices have at
+ * most 256 chunks (one partial-sum slot each), int32 matrices at most 2^16.
+ * EINVAL for bad arguments, EOVERFLOW when C(n, m) >= 2^63. */
+int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uint64_t *hChunk,
+                              uint64_t *hChunks);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,7 @@ SIGNATURES = {
     "radic_host_binomial": (_i, [_i, _i, _u64p]),
     "radic_host_unrank": (_i, [_i, _i, _u64, _ip]),
     "radic_host_prime": (_i, [_i, _u32p]),
+    "radic_host_batch_chunking": (_i, [_i, _i, _i, _i, _u64p, _u64p]),
     "radic_set_prime_set": (_i, [_u32p, _i]),
 }
 
@@ -350,12 +351,21 @@ def host_prime(i):
     return int(p.value)
 
 
+def host_batch_chunking(dtype, m, n, subsets_per_lane):
+    """(ranks per chunk, chunks) of one matrix in radic_det_batched."""
+    c, k = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    _check(lib().radic_host_batch_chunking(int(dtype), int(m), int(n), int(subsets_per_lane), ctypes.byref(c),
+                                           ctypes.byref(k)), "radic_host_batch_chunking")
+    return int(c.value), int(k.value)
+
+
 # ------------------------------------------------------------------ batched
 class Batch:
     """Device buffers for radic_det_batched: entry pools, descriptors, results and
-    workspace, built from a list of 2-D numpy arrays (float64 or int32)."""
+    workspace, built from a list of 2-D numpy arrays (float64 or int32).  With
+    work=False no workspace is made."""
 
-    def __init__(self, matrices, device="cuda"):
+    def __init__(self, matrices, device="cuda", work=True):
         torch = _torch()
         f64, i32, desc = [], [], np.zeros(len(matrices), dtype=DESC_DTYPE)
         foff = ioff = 0
@@ -378,7 +388,7 @@ class Batch:
         self.f64 = torch.from_numpy(np.concatenate(f64) if f64 else np.zeros(1)).to(device)
         self.i32 = torch.from_numpy(np.concatenate(i32) if i32 else np.zeros(1, np.int32)).to(device)
         self.out = torch.zeros(self.batch * BATCH_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device)
-        self.work = workspace(RADIC_WS_BATCHED, batch=self.batch, device=device)
+        self.work = workspace(RADIC_WS_BATCHED, batch=self.batch, device=device) if work else None
 
     def args(self, precision):
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)

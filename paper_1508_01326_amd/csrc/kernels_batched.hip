@@ -35,6 +35,7 @@ struct BatchMeta {
     int kind;                    // 0 float, 1 exact, -1 no work (error or m > n)
     int n_primes;
     int scale_exp;               // FP32_BULK: sum of the row exponents
+    int all_double;              // FP32_BULK with fewer than kF32MinMinors minors: every minor in double
 };
 
 // Work classes: (kind, m), kind 0 float / 1 exact, m = 1..RADIC_MAX_M.  Each
@@ -43,12 +44,32 @@ struct BatchMeta {
 constexpr int kClasses = 2 * RADIC_MAX_M;
 __host__ __device__ inline int class_of(int kind, int m) { return kind * RADIC_MAX_M + (m - 1); }
 
+// Queue counters are 64-bit: a class's chunk total is a sum over its matrices
+// of up to 2^16 chunks each (see k_batch_setup), so it can pass 2^32, and a
+// 32-bit counter would wrap and never reach it.
 struct BatchHeader {
     unsigned long long chunks[kClasses];   // queue length per class
-    unsigned int queue[kClasses];          // next chunk index per class
+    unsigned long long queue[kClasses];    // next chunk index per class
 };
 
-static_assert(sizeof(BatchHeader) == 8 * kClasses + 4 * kClasses, "batch header layout");
+static_assert(sizeof(BatchHeader) == 16 * kClasses, "batch header layout");
+
+// Exact chunks hold at least 64 * spl_int ranks and are made larger for big
+// rank spaces, so that no matrix has more than kExactChunksMax of them.
+constexpr unsigned long long kExactChunksMax = 1ull << 16;
+
+// Chunk size (a multiple of 64 ranks, at least 64 * spl) and chunk count of one
+// matrix with `total` ranks: float chunks are at most kBatchChunksPerMatrix per
+// matrix (each has a partial-sum slot), exact chunks at most kExactChunksMax.
+__host__ __device__ inline void batch_chunking(int kind, unsigned long long total, int spl,
+                                               unsigned long long& chunk, unsigned long long& nchunks) {
+    const unsigned long long most = kind == 0 ? (unsigned long long)kBatchChunksPerMatrix : kExactChunksMax;
+    const unsigned long long minc = 64ull * (unsigned long long)(spl > 0 ? spl : 1);
+    unsigned long long c = (total + most - 1) / most;
+    c = (c + 63) & ~63ull;
+    chunk = c > minc ? c : minc;
+    nchunks = (total + chunk - 1) / chunk;
+}
 
 struct BatchJob {
     const radic_matrix_desc* desc;
@@ -106,11 +127,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
         } else if (d.dtype == 0) {
             mt.kind = 0;
             mt.total = total;
-            const unsigned long long minc = 64ull * (unsigned long long)J.spl_float;
-            unsigned long long c = (total + kBatchChunksPerMatrix - 1) / kBatchChunksPerMatrix;
-            c = (c + 63) & ~63ull;
-            mt.chunk = c > minc ? c : minc;
-            mt.nchunks = (total + mt.chunk - 1) / mt.chunk;
+            batch_chunking(0, total, J.spl_float, mt.chunk, mt.nchunks);
             const double* A = J.f64 + d.offset;
             int se = 0, bad = 0;
             for (int i = 0; i < d.m; ++i) {
@@ -125,6 +142,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
                 se += e;
             }
             mt.scale_exp = J.prec == RADIC_FP32_BULK ? se : 0;
+            mt.all_double = J.prec == RADIC_FP32_BULK && total < kF32MinMinors;
             if (bad) {
                 mt.status = RADIC_ENONFINITE;
                 mt.kind = -1;
@@ -154,8 +172,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
                 mt.kind = 1;
                 mt.total = total;
                 mt.n_primes = k;
-                mt.chunk = 64ull * (unsigned long long)J.spl_int;
-                mt.nchunks = (total + mt.chunk - 1) / mt.chunk;
+                batch_chunking(1, total, J.spl_int, mt.chunk, mt.nchunks);
             }
         }
     }
@@ -192,15 +209,15 @@ __global__ __launch_bounds__(1024) void k_batch_scan(BatchJob J) {
     if (threadIdx.x == blockDim.x - 1) {
         prefix[J.batch] = sf[blockDim.x - 1];
         J.header->chunks[cls] = sf[blockDim.x - 1];
-        J.header->queue[cls] = 0u;
+        J.header->queue[cls] = 0ull;
     }
 }
 
 // ---------------------------------------------------------------- queue helpers
-__device__ __forceinline__ unsigned long long take_chunk(unsigned int* queue, int lane) {
-    unsigned int g = 0;
-    if (lane == 0) g = atomicAdd(queue, 1u);
-    return (unsigned long long)__shfl(g, 0, kWave);
+__device__ __forceinline__ unsigned long long take_chunk(unsigned long long* queue, int lane) {
+    unsigned long long g = 0;
+    if (lane == 0) g = atomicAdd(queue, 1ull);
+    return __shfl(g, 0, kWave);
 }
 
 // matrix b with prefix[b] <= g < prefix[b + 1] (prefix nondecreasing, prefix[0] = 0)
@@ -266,7 +283,7 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
     const int n = d.n;
     const T* colbase = F32 ? reinterpret_cast<const T*>(L.cf) : reinterpret_cast<const T*>(L.cd);
     const int colstride = F32 ? ST32 : ST64;
-    const T tau = (T)J.tau;
+    const T tau = mt.all_double ? (T)__builtin_inf() : (T)J.tau;
     const unsigned long long sub = mt.chunk / kWave;          // ranks per lane
     const unsigned long long q0 = c * mt.chunk + (unsigned long long)lane * sub;
     const int cnt = q0 < mt.total ? (int)((mt.total - q0) < sub ? (mt.total - q0) : sub) : 0;
@@ -559,35 +576,43 @@ __global__ __launch_bounds__(256) void k_batch_finalize(BatchJob J) {
 hipError_t upload_binomials_batched(const unsigned long long* t) { return upload_binomial_table(t); }
 hipError_t upload_primes_batched(const unsigned* primes, int count) { return upload_prime_table(primes, count); }
 size_t batched_workspace_bytes(int batch) { return batch_ws_bytes(batch); }
+void host_batch_chunking(int kind, unsigned long long total, int spl, unsigned long long* chunk,
+                         unsigned long long* nchunks) {
+    batch_chunking(kind, total, spl, *chunk, *nchunks);
+}
 
-// Persistent grid: as many workgroups as fit on the device at once.
-static int persistent_grid(const void* kernel, int block) {
+// Persistent grid: as many workgroups as fit on the current device at once,
+// cached per (kernel, device).
+constexpr int kMaxDevices = 64;
+static int persistent_grid(const void* kernel, int block, int (&cache)[kMaxDevices]) {
     int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return 256;
+    if (cache[dev] > 0) return cache[dev];
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, block, 0) != hipSuccess || per <= 0) per = 1;
-    return cus * per;
+    cache[dev] = cus * per;
+    return cache[dev];
 }
 
 template <bool F32, int M>
 static hipError_t launch_float_class(const BatchJob& J, hipStream_t s) {
-    static int grid = 0;
+    static int grid[kMaxDevices] = {};
     const int block = kBatchWaves * kWave;
-    if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_float<F32, M>), block);
-    hipLaunchKernelGGL((k_batch_float<F32, M>), dim3(grid), dim3(block), 0, s, J);
+    const int g = persistent_grid(reinterpret_cast<const void*>(k_batch_float<F32, M>), block, grid);
+    hipLaunchKernelGGL((k_batch_float<F32, M>), dim3(g), dim3(block), 0, s, J);
     return hipGetLastError();
 }
 
 template <int M>
 static hipError_t launch_int_class(const BatchJob& J, hipStream_t s) {
-    static int grid = 0;
+    static int grid[kMaxDevices] = {};
     const int block = kBatchWaves * kWave;
     if constexpr (M <= 10) {
-        if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int_w2<M>), block);
-        hipLaunchKernelGGL(k_batch_int_w2<M>, dim3(grid), dim3(block), 0, s, J);
+        const int g = persistent_grid(reinterpret_cast<const void*>(k_batch_int_w2<M>), block, grid);
+        hipLaunchKernelGGL(k_batch_int_w2<M>, dim3(g), dim3(block), 0, s, J);
     } else {
-        if (!grid) grid = persistent_grid(reinterpret_cast<const void*>(k_batch_int<M>), block);
-        hipLaunchKernelGGL(k_batch_int<M>, dim3(grid), dim3(block), 0, s, J);
+        const int g = persistent_grid(reinterpret_cast<const void*>(k_batch_int<M>), block, grid);
+        hipLaunchKernelGGL(k_batch_int<M>, dim3(g), dim3(block), 0, s, J);
     }
     return hipGetLastError();
 }

@@ -331,11 +331,19 @@ __global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J, int
             } else if (J.mapping == 1) {
                 if constexpr (M >= 3) {
                     // the blocks of m-2 column prefixes this wave of the float launch was given
-                    const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+                    const unsigned long long nblk =
+                        J.colex ? J.colex_blocks : (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+                    // a colex block prefix by prefix, a dictionary block whole
                     for (unsigned long long blk = gw; blk < nblk; blk += nw) {
-                        unsigned long long r0, r1;
-                        prefix_block_ranks<M>(J, bt, prefix_block(J, blk), r0, r1);
-                        redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                        unsigned long long t0 = 0;
+                        int segs = 1;
+                        if (J.colex) colex_block<M - 2>(blk, J.n, bt, M, J.colex_pairs, lane, t0, segs);
+                        for (int sgm = 0; sgm < segs; ++sgm) {
+                            unsigned long long r0, r1;
+                            if (J.colex) colex_prefix_ranks<M>(J, bt, t0 + (unsigned long long)sgm, r0, r1);
+                            else prefix_block_ranks<M>(J, bt, blk, r0, r1);
+                            redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                        }
                     }
                 }
             } else {
@@ -418,6 +426,9 @@ __device__ __forceinline__ void add_partials(const Partial* parts, int G, double
     }
 }
 
+// use_scale: bit 0 scales by 2^(sum of the row exponents) (FP32-bulk), bit 1
+// reports every minor as done in double (an FP32-bulk call over too few minors
+// for a float sum, run by the double kernel).
 __global__ __launch_bounds__(512) void k_finalize_float(const Partial* parts, int G, const Partial* fb_parts, int G2,
                                                          const DetHeader* h, radic_f64_result* out,
                                                          unsigned long long count, int use_scale) {
@@ -444,14 +455,14 @@ __global__ __launch_bounds__(512) void k_finalize_float(const Partial* parts, in
             sa += red[4 * w + 2];
             sn += redn[w];
         }
-        const int e = use_scale ? h->scale_exp : 0;
+        const int e = (use_scale & 1) ? h->scale_exp : 0;
         radic_f64_result r;
         r.hi = ldexp(sh, e);
         r.lo = ldexp(sl, e);
         r.abs_sum = ldexp(sa, e);
         r.value = r.hi + r.lo;
         r.n_subsets = count;
-        r.n_fallback = sn;
+        r.n_fallback = (use_scale & 2) ? count : sn;   // bit 1: every minor was done in double
         r.status = h->nonfinite ? RADIC_ENONFINITE : RADIC_OK;
         r.reserved = 0;
         if (h->nonfinite) r.value = __builtin_nan("");

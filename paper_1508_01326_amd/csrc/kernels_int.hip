@@ -166,7 +166,9 @@ struct IntSharedJob {
     int grid_x;
     unsigned long long q_begin, count, total, n_prefix, p_begin, p_end;
     double* partials;             // [prime][grid_x] residues
-    const unsigned* block_order;  // prefix block behind each block slot (heaviest first), or null
+    int colex;                    // 1: colex blocks of the whole rank space (see colex_block)
+    unsigned colex_pairs;
+    unsigned long long colex_blocks;
 };
 
 template <int M> __host__ __device__ int int_shared_lds_bytes(int n, int waves, int cap) {
@@ -202,18 +204,26 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
     __syncthreads();
 
     double acc = 0.0;   // this lane's sum of signed minors mod p
-    const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+    const unsigned long long nblk = J.colex ? J.colex_blocks : (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
     const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
     const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
     for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
-        const unsigned long long pb = J.block_order ? (unsigned long long)J.block_order[blk] : blk;
-        const unsigned long long next = J.p_begin + pb * kPrefixBlock;
-        const unsigned long long pe = next + kPrefixBlock;
-        const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
-        unsigned long long r0, r1;
-        prefix_block_ranks<M>(J, bt, pb, r0, r1);
-        const unsigned long long rbase = first_completion_rank<M>(next, J, bt);
-        int_prefix_range<M>(cr, n, bt, M, next, pi1, J.n_prefix, rbase, r0, r1, p, pinv, J.cap, slot, incl, tv, lane, acc);
+        unsigned long long next = J.p_begin + blk * kPrefixBlock;
+        unsigned long long pi1 = next + kPrefixBlock < J.p_end ? next + kPrefixBlock : J.p_end;
+        if (J.colex) {
+            int cnt;
+            colex_block<M - 2>(blk, n, bt, M, J.colex_pairs, lane, next, cnt);
+            pi1 = next + (unsigned long long)cnt;
+            // colex blocks come heaviest first (prefixes with the most later columns)
+            int_prefix_range<M, true>(cr, n, bt, M, next, pi1, J.n_prefix, 0ull, 0ull, J.total, p, pinv, J.cap,
+                                      slot, incl, tv, lane, acc);
+        } else {
+            unsigned long long r0, r1;
+            prefix_block_ranks<M>(J, bt, blk, r0, r1);
+            const unsigned long long rbase = first_completion_rank<M>(next, J, bt);
+            int_prefix_range<M>(cr, n, bt, M, next, pi1, J.n_prefix, rbase, r0, r1, p, pinv, J.cap, slot, incl, tv,
+                                lane, acc);
+        }
     }
     // fixed-order sum over the wave, then waves in order
 #pragma unroll
@@ -334,8 +344,8 @@ int int_shared_lds(int m, int n, int waves, int cap) {
 }
 
 hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
-                             unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
-                             const unsigned* block_order, hipStream_t s) {
+                             unsigned long long n_prefix, unsigned colex_pairs, unsigned long long colex_blocks,
+                             int cap, int grid_x, int n_primes, int block, void* ws, hipStream_t s) {
     IntSharedJob J{};
     J.A = A;
     J.lda = lda;
@@ -348,7 +358,9 @@ hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned
     J.n_prefix = n_prefix;
     J.p_begin = 0;
     J.p_end = n_prefix;
-    J.block_order = block_order;
+    J.colex = 1;
+    J.colex_pairs = colex_pairs;
+    J.colex_blocks = colex_blocks;
     J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
     const int lds = int_shared_lds(m, n, block / kWave, cap);
     switch (m) {

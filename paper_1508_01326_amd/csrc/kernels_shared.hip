@@ -7,7 +7,9 @@
 // Those steps are done once per prefix here; what is left of each minor is the
 // last two steps on a 2 x 2 block.
 //
-// A wave takes a block of 64 consecutive prefixes and works in rounds:
+// A wave takes a block of 64 consecutive prefixes (in colex order for a whole
+// rank space, which puts the prefixes with the most later columns first, or in
+// dictionary order for a rank range) and works in rounds:
 //  A. Each lane takes one prefix and factors the m x (m-2) block of its columns
 //     by LU with partial pivoting in registers, column by column (the first m-2
 //     steps of every minor with that prefix).  From the multipliers it forms
@@ -116,20 +118,30 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     int gcount = 0;          // wave-uniform number of flagged minors (FP32-bulk)
     bool overflow = false;   // wave-uniform: more flagged minors than the segment holds
     const unsigned long long qend = J.q_begin + J.count;
-    const unsigned long long nblk = (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
+    const unsigned long long nblk = J.colex ? J.colex_blocks : (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
     const unsigned long long gwave = (unsigned long long)blockIdx.x * waves + wave;
     const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
 
     for (unsigned long long blk = gwave; blk < nblk && !overflow; blk += nwaves) {
-        unsigned long long next = J.p_begin + prefix_block(J, blk) * kPrefixBlock;
-        const unsigned long long pe = next + kPrefixBlock;
-        const unsigned long long pi1 = pe < J.p_end ? pe : J.p_end;
+        // colex blocks (whole rank space) hold colex numbers; otherwise 64
+        // dictionary numbers from p_begin
+        unsigned long long next, pi1;
+        if (J.colex) {
+            int cnt;
+            colex_block<P>(blk, n, bt, BS, J.colex_pairs, lane, next, cnt);
+            pi1 = next + (unsigned long long)cnt;
+        } else {
+            next = J.p_begin + blk * kPrefixBlock;
+            const unsigned long long pe = next + kPrefixBlock;
+            pi1 = pe < J.p_end ? pe : J.p_end;
+        }
         while (next < pi1 && !overflow) {
             // ---------------- the round's prefixes: lane l takes prefix next + l
             const unsigned long long pi = next + lane;
             const bool have = pi < pi1;
             int c[P];
-            unrank_prefix<P>(have ? pi : next, n, J.n_prefix, bt, BS, c);
+            if (J.colex) unrank_prefix_colex<P>(have ? pi : next, n, bt, BS, c);
+            else unrank_prefix<P>(have ? pi : next, n, J.n_prefix, bt, BS, c);
             const int r = n - 1 - c[P - 1];
             // dictionary rank of the prefix's first sequence (c, c_{m-3}+1, c_{m-3}+2):
             // the sequences after it number sum_k C(n-1-c_k, m-k)

@@ -237,12 +237,10 @@ __device__ __forceinline__ double refactor_entry_f64(const double* cd, const uns
 // and fused multiply-adds of lu_steps.  The permutation's parity is the number
 // of unused rows above each pivot row, summed.  Every lane returns the term.
 template <int M, int ST64 = Layout<M>::st64>
-__device__ __forceinline__ double group_refactor_f64(const double* cd, const unsigned* entry, int lane,
-                                                     double& absdet) {
+__device__ __forceinline__ double group_refactor_cols_f64(const double* cd, const int (&c)[M], int lane,
+                                                          double& absdet) {
     static_assert(M <= 8, "one row per lane of a group of eight");
     const int r = lane & 7, base = lane & ~7;
-    int c[M];
-    unpack_cols<M>(entry, c);
     double a[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) a[j] = r < M ? cd[c[j] * ST64 + r] : 0.0;
@@ -276,6 +274,15 @@ __device__ __forceinline__ double group_refactor_f64(const double* cd, const uns
     const double d = zero ? 0.0 : det;
     absdet = fabs(d);
     return (radic_sign_odd<M>(c) ^ odd) ? -d : d;
+}
+
+// The same for a queued (packed) minor.
+template <int M, int ST64 = Layout<M>::st64>
+__device__ __forceinline__ double group_refactor_f64(const double* cd, const unsigned* entry, int lane,
+                                                     double& absdet) {
+    int c[M];
+    unpack_cols<M>(entry, c);
+    return group_refactor_cols_f64<M, ST64>(cd, c, lane, absdet);
 }
 
 // Refactor queued minors in double, one minor per lane; lane l takes entries

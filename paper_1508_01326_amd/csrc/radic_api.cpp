@@ -39,12 +39,14 @@ hipError_t launch_2xn(const double* A, long long lda, long long n, int G, void* 
 hipError_t upload_binomials_wide(const unsigned long long* host_table);
 hipError_t launch_wide(const FloatJob& J, int spl, int grid, hipStream_t s);
 hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned long long total,
-                             unsigned long long n_prefix, int cap, int grid_x, int n_primes, int block, void* ws,
-                             const unsigned* block_order, hipStream_t s);
+                             unsigned long long n_prefix, unsigned colex_pairs, unsigned long long colex_blocks,
+                             int cap, int grid_x, int n_primes, int block, void* ws, hipStream_t s);
 size_t int_workspace_bytes();
 hipError_t upload_binomials_batched(const unsigned long long* t);
 hipError_t upload_primes_batched(const unsigned* primes, int count);
 size_t batched_workspace_bytes(int batch);
+void host_batch_chunking(int kind, unsigned long long total, int spl, unsigned long long* chunk,
+                         unsigned long long* nchunks);
 hipError_t launch_batched(const radic_matrix_desc* desc, int batch, const double* f64, const int* i32, int prec,
                           double tau, int spl_float, int spl_int, int prime_count, radic_batch_result* out,
                           void* ws, hipStream_t s);
@@ -89,6 +91,13 @@ static int device_error(const char* what, hipError_t e) {
     if (std::getenv("RADIC_LOG")) std::fprintf(stderr, "[radic] %s\n", g_last_error);
     return RADIC_EDEVICE;
 }
+
+static int host_error(int status, const char* what) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "%s", what);
+    if (std::getenv("RADIC_LOG")) std::fprintf(stderr, "[radic] %s\n", g_last_error);
+    return status;
+}
+
 
 // ---------------------------------------------------------------- primes of the exact path
 // Deterministic Miller-Rabin: bases 2, 3, 5, 7 decide every n < 3,215,031,751.
@@ -185,7 +194,12 @@ static int ensure_device(int* lds_limit = nullptr) {
 struct Shape {
     int spl;
     int block;
+    bool spl_set = false;   // spl tuned or forced (not the default)
 };
+// Prefix-shared paths: about 64 * spl minors per colex block (subsets per lane
+// per block); their default spl.
+constexpr int kSharedSplFloat = 64;
+constexpr int kSharedSplInt = 48;
 static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;   // (kind, prec, m, n) -> shape
 static int g_force_spl = 0, g_force_block = 0;
 static int g_enumeration = RADIC_ENUM_AUTO;
@@ -207,8 +221,14 @@ static Shape pick_shape(int kind, int prec, int m, int n) {
     {
         std::lock_guard<std::mutex> lk(g_mu);
         auto it = g_tuned.find(std::make_tuple(kind, prec, m, n));
-        if (it != g_tuned.end()) s = it->second;
-        if (g_force_spl > 0) s.spl = g_force_spl;
+        if (it != g_tuned.end()) {
+            s = it->second;
+            s.spl_set = true;
+        }
+        if (g_force_spl > 0) {
+            s.spl = g_force_spl;
+            s.spl_set = true;
+        }
         if (g_force_block > 0) s.block = g_force_block;
     }
     return s;
@@ -289,81 +309,20 @@ struct KernelTimer {
     }
 };
 
-// ---------------------------------------------------------------- block order
-// Heaviest-first order of the prefix blocks of a whole-matrix prefix-shared
-// launch (the float kernel and, per prime, the exact one).  Block slots go to waves in index order and workgroups are dispatched
-// in index order, so with the heaviest blocks first the last workgroups to start
-// hold light blocks and finish close together (longest processing time first).
-// A block's cost is modelled from the kernel's own round structure: per round
-// (lanes take prefixes while their projected columns fit the cap) a fixed part,
-// a part per column-run of the projection and a part per minor-run of the pair
-// loop, each run being one lane's share of 64.  The weights are cycle estimates
-// of those parts; only their ratios matter.  One table per device and shape
-// (m, n, cap), built and uploaded on the first whole-matrix call and kept until
-// the process ends, so a shape's launches always sum in the same order; a call
-// under stream capture uses a table that already exists, else dictionary order.
-constexpr unsigned long long kOrderMaxBlocks = 1ull << 16;   // 4 Mi prefixes
-static std::map<std::tuple<int, int, int, int>, unsigned*> g_block_order;
-
-static const unsigned* block_order(int m, int n, int cap, unsigned long long n_prefix, hipStream_t stream) {
-    const unsigned long long nblk = (n_prefix + kPrefixBlock - 1) / kPrefixBlock;
-    if (m < 3 || nblk < 2 || nblk > kOrderMaxBlocks) return nullptr;
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    const auto key = std::make_tuple(dev, m, n, cap);
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto it = g_block_order.find(key);
-    if (it != g_block_order.end()) return it->second;
-    // building one allocates: not while the stream is being captured
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-    constexpr double kRound = 13300.0, kColRun = 1600.0, kMinorRun = 530.0;
-    // r = n - 1 - (last prefix column) for every prefix, in dictionary order of
-    // the (m-2)-subsets of the first n-2 columns
-    const int P = m - 2, N = n - 2;
-    std::vector<int> c(P);
-    for (int k = 0; k < P; ++k) c[k] = k;
-    std::vector<double> cost(nblk, 0.0);
-    std::vector<int> rb;
-    rb.reserve(kPrefixBlock);
-    unsigned long long p = 0;
-    for (unsigned long long b = 0; b < nblk; ++b) {
-        rb.clear();
-        for (int l = 0; l < kPrefixBlock && p < n_prefix; ++l, ++p) {
-            rb.push_back(n - 1 - c[P - 1]);
-            int k = P - 1;   // next subset in dictionary order
-            while (k >= 0 && c[k] == N - P + k) --k;
-            if (k >= 0) {
-                ++c[k];
-                for (int j = k + 1; j < P; ++j) c[j] = c[j - 1] + 1;
-            }
-        }
-        size_t i = 0;
-        while (i < rb.size()) {
-            unsigned cols = 0, minors = 0;
-            size_t t = i;
-            while (t < rb.size() && cols + (unsigned)rb[t] <= (unsigned)cap) {
-                cols += (unsigned)rb[t];
-                minors += (unsigned)(rb[t] * (rb[t] - 1) / 2);
-                ++t;
-            }
-            if (t == i) t = i + 1;   // the kernel always takes the first prefix
-            cost[b] += kRound + kColRun * (double)(((cols + kWave - 1) / kWave) | 1u) +
-                       kMinorRun * (double)((minors + kWave - 1) / kWave);
-            i = t;
-        }
+// ---------------------------------------------------------------- colex blocks
+// Number of colex blocks of the prefixes of m-2 columns out of the first n-2
+// (the kernels' colex_block): per last column v, C(v, m-3) prefixes in runs of
+// colex_run(n-1-v, K).
+static unsigned long long colex_block_count(int m, int n, unsigned K) {
+    const int P = m - 2;
+    unsigned long long total = 0;
+    for (int v = P - 1; v <= n - 3; ++v) {
+        unsigned long long cnt = 0;
+        host_binomial(v, P - 1, &cnt);
+        const unsigned long long k = (unsigned long long)colex_run(n - 1 - v, K);
+        total += (cnt + k - 1) / k;
     }
-    std::vector<unsigned> order(nblk);
-    for (unsigned long long b = 0; b < nblk; ++b) order[b] = (unsigned)b;
-    std::stable_sort(order.begin(), order.end(), [&](unsigned x, unsigned y) { return cost[x] > cost[y]; });
-    unsigned* d = nullptr;
-    if (hipMalloc(reinterpret_cast<void**>(&d), sizeof(unsigned) * nblk) != hipSuccess) return nullptr;
-    if (hipMemcpy(d, order.data(), sizeof(unsigned) * nblk, hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        return nullptr;
-    }
-    g_block_order.emplace(key, d);
-    return d;
+    return total;
 }
 
 // ---------------------------------------------------------------- validation helpers
@@ -379,12 +338,25 @@ static size_t ws_partials() { return kHeaderBytes; }
 static size_t ws_fb_partials() { return ws_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
 static size_t ws_fb_count() { return ws_fb_partials() + sizeof(Partial) * (size_t)kMaxGrid; }
 static size_t ws_fb_entries() { return ws_fb_count() + sizeof(unsigned) * (size_t)kMaxGrid * 4; }
-static size_t det_workspace_bytes() { return ws_fb_entries() + 16 * (size_t)kDeferEntries; }
+// FP32-bulk deferral entries for an m x n matrix: one per 64 minors (several
+// times the flagged share of random minors, a few per mille), at least
+// kDeferEntries and at most kDeferEntriesMax.  A wave whose share overflows
+// redoes its blocks in double, which is correct but slow.
+constexpr unsigned long long kDeferEntriesMax = 1ull << 25;
+static unsigned long long defer_entries_for(int m, int n) {
+    unsigned long long total = 0;
+    if (m >= 1 && n >= m && host_binomial(n, m, &total) != RADIC_OK) total = ~0ull;
+    unsigned long long e = total / 64;
+    if (e < (unsigned long long)kDeferEntries) e = kDeferEntries;
+    if (e > kDeferEntriesMax) e = kDeferEntriesMax;
+    return e;
+}
+static size_t det_workspace_bytes(int m, int n) { return ws_fb_entries() + 16 * (size_t)defer_entries_for(m, n); }
 
 // Deferral entries per wave for a launch of `grid` workgroups of `block` threads.
-static int defer_cap_for(int grid, int block) {
+static int defer_cap_for(int grid, int block, unsigned long long entries) {
     const long long waves = (long long)grid * (block / kWave);
-    long long c = kDeferEntries / (waves > 0 ? waves : 1);
+    long long c = (long long)entries / (waves > 0 ? waves : 1);
     if (c > 4096) c = 4096;
     return (int)c;
 }
@@ -499,7 +471,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     if (m > n) return zero_result(dOut, stream);
     unsigned long long total = 0;
     if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
-    if ((rc = check_workspace(dWork, work_bytes, det_workspace_bytes())) != RADIC_OK) return rc;
+    if ((rc = check_workspace(dWork, work_bytes, det_workspace_bytes(m, n))) != RADIC_OK) return rc;
     if (whole) {
         q_begin = 0;
         count = total;
@@ -533,6 +505,10 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         e = launch_finalize_float(J.partials, grid, nullptr, 0, J.header, dOut, count, 0, stream);
         return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
     }
+    // FP32-bulk over fewer minors than a float sum can absorb: the double
+    // kernel, with every minor reported as done in double
+    const bool all_double = prec == RADIC_FP32_BULK && count < kF32MinMinors;
+    if (all_double) prec = RADIC_FP64;
     Shape sh = pick_shape(RADIC_WS_DET, prec, m, n);
     if (!fit_lds(m, n, prec, sh)) return RADIC_ENOTSUP;
 
@@ -578,17 +554,20 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
             J.mapping = 0;
         } else {
             sh.block = block;
-            if (kt == 2 && J.p_begin == 0 && J.p_end == J.n_prefix)
-                J.block_order = block_order(m, n, J.cap, J.n_prefix, stream);
+            // a whole rank space takes its prefixes in colex blocks (heaviest first)
+            J.colex = (kt == 2 && J.p_begin == 0 && J.p_end == J.n_prefix) ? 1 : 0;
+            J.colex_pairs = 64u * (unsigned)(sh.spl_set ? sh.spl : kSharedSplFloat);
+            J.colex_blocks = J.colex ? colex_block_count(m, n, J.colex_pairs) : 0;
             const unsigned long long per_block = kt == 2 ? kPrefixBlock : kGroupBlock;
-            const unsigned long long blocks = (J.p_end - J.p_begin + per_block - 1) / per_block;
+            const unsigned long long blocks =
+                J.colex ? J.colex_blocks : (J.p_end - J.p_begin + per_block - 1) / per_block;
             const unsigned long long wpb = (unsigned long long)(block / kWave);
             unsigned long long g = (blocks + wpb - 1) / wpb;
             grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
         }
     }
     const bool defer = prec == RADIC_FP32_BULK;
-    J.defer_cap = defer_cap_for(grid, sh.block);
+    J.defer_cap = defer_cap_for(grid, sh.block, (work_bytes - ws_fb_entries()) / 16);
     hipError_t e;
     {
         KernelTimer timer;
@@ -605,7 +584,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
         if (e != hipSuccess) return device_error("launch of the refactorisation kernel", e);
     }
     e = launch_finalize_float(J.partials, grid, refactor ? J.fb_partials : nullptr, refactor_grid(grid, sh.block),
-                              J.header, dOut, count, defer, stream);
+                              J.header, dOut, count, (defer ? 1 : 0) | (all_double ? 2 : 0), stream);
     return e == hipSuccess ? RADIC_OK : device_error("launch of the finalize kernel", e);
 }
 
@@ -696,7 +675,7 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch) {
     switch (kind) {
         case RADIC_WS_DET:
             if (m < 1 || n < 1) return 0;
-            return det_workspace_bytes();
+            return det_workspace_bytes(m, n);
         case RADIC_WS_INT:
             if (m < 1 || n < 1) return 0;
             return int_workspace_bytes();
@@ -757,7 +736,7 @@ int radic_det_subsets(const double* dA, int m, int n, int64_t lda, int prec, uin
 int radic_det_2xn(const double* dA, int64_t n, int64_t lda, radic_f64_result* dOut, void* dWork, size_t work_bytes,
                   hipStream_t stream) {
     if (!dA || !dOut || n < 1 || lda < n) return RADIC_EINVAL;
-    int rc = check_workspace(dWork, work_bytes, det_workspace_bytes());
+    int rc = check_workspace(dWork, work_bytes, det_workspace_bytes(2, 2));
     if (rc != RADIC_OK) return rc;
     if ((rc = ensure_device()) != RADIC_OK) return rc;
     if (n < 2) return zero_result(dOut, stream);   // m = 2 > n: zero (Definition 3)
@@ -818,13 +797,13 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     if (shared) {
         unsigned long long n_prefix = 0;
         host_binomial(n - 2, m - 2, &n_prefix);
-        const unsigned long long blocks = (n_prefix + 63) / 64;
+        const unsigned K = 64u * (unsigned)(sh.spl_set ? sh.spl : kSharedSplInt);
+        const unsigned long long blocks = colex_block_count(m, n, K);
         const unsigned long long wpb = (unsigned long long)(block / kWave);
         unsigned long long g = (blocks + wpb - 1) / wpb;
         grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));
-        const unsigned* order = block_order(m, n, cap, n_prefix, stream);
         KernelTimer timer;
-        e = launch_int_shared(dA, m, n, lda, total, n_prefix, cap, grid, k, block, dWork, order, stream);
+        e = launch_int_shared(dA, m, n, lda, total, n_prefix, K, blocks, cap, grid, k, block, dWork, stream);
     } else {
         const unsigned long long chunks = (total + sh.spl - 1) / sh.spl;
         grid = grid_for(chunks, sh.block);
@@ -849,15 +828,10 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     return RADIC_OK;
 }
 
-int radic_det_batched(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32, int prec,
-                      radic_batch_result* dOut, void* dWork, size_t work_bytes, hipStream_t stream) {
-    if (!dDesc || !dOut || batch < 0) return RADIC_EINVAL;
-    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
-    if (batch == 0) return RADIC_OK;
-    if (batch > (1 << 24)) return RADIC_ENOTSUP;
-    int rc = check_workspace(dWork, work_bytes, batched_workspace_bytes(batch));
-    if (rc != RADIC_OK) return rc;
-    if ((rc = ensure_device()) != RADIC_OK) return rc;
+// The batched launch sequence on a workspace that has been checked; `timed`
+// lets the timing hook time it.
+static int batched_launch(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32,
+                          int prec, radic_batch_result* dOut, void* dWork, hipStream_t stream, bool timed) {
     const Shape sf = pick_shape(RADIC_WS_BATCHED, prec, 0, 0);
     const Shape si = pick_shape(RADIC_WS_BATCHED, 2, 0, 0);
     double tau;
@@ -868,12 +842,27 @@ int radic_det_batched(const radic_matrix_desc* dDesc, int batch, const double* d
         prime_count = (int)g_primes.size();
     }
     hipError_t e;
-    {
+    if (timed) {
         ProfScope ps(stream);
+        e = launch_batched(dDesc, batch, dF64, reinterpret_cast<const int*>(dI32), prec, tau, sf.spl, si.spl,
+                           prime_count, dOut, dWork, stream);
+    } else {
         e = launch_batched(dDesc, batch, dF64, reinterpret_cast<const int*>(dI32), prec, tau, sf.spl, si.spl,
                            prime_count, dOut, dWork, stream);
     }
     return e == hipSuccess ? RADIC_OK : device_error("launch of the batched kernels", e);
+}
+
+int radic_det_batched(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32, int prec,
+                      radic_batch_result* dOut, void* dWork, size_t work_bytes, hipStream_t stream) {
+    if (!dDesc || !dOut || batch < 0) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (batch == 0) return RADIC_OK;
+    if (batch > (1 << 24)) return RADIC_ENOTSUP;
+    int rc = check_workspace(dWork, work_bytes, batched_workspace_bytes(batch));
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    return batched_launch(dDesc, batch, dF64, dI32, prec, dOut, dWork, stream, true);
 }
 
 struct GraphHandle {
@@ -975,11 +964,11 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
         for (double& x : hf) x = rng.uniform();
         double* dA = static_cast<double*>(buf.alloc(hf.size() * 8));
         void* out = buf.alloc(sizeof(radic_f64_result));
-        void* ws = buf.alloc(det_workspace_bytes());
+        void* ws = buf.alloc(det_workspace_bytes(m, n));
         if (!dA || !out || !ws) return RADIC_ENOMEM;
         if (hipMemcpy(dA, hf.data(), hf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return RADIC_EDEVICE;
         run = [=]() { return radic_det(dA, m, n, n, prec, static_cast<radic_f64_result*>(out), ws,
-                                       det_workspace_bytes(), stream); };
+                                       det_workspace_bytes(m, n), stream); };
     } else if (kind == RADIC_WS_INT) {
         hi.resize((size_t)m * n);
         for (int& x : hi) x = (int)(rng.next() % 19) - 9;
@@ -1182,6 +1171,18 @@ int radic_host_unrank(int m, int n, uint64_t q, int* hCols) {
         hCols[k] = c + 1;
         ++c;
     }
+    return RADIC_OK;
+}
+
+int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uint64_t* hChunk, uint64_t* hChunks) {
+    if (!hChunk || !hChunks || (dtype != 0 && dtype != 1) || m < 1 || n < m || subsets_per_lane < 1)
+        return RADIC_EINVAL;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
+    unsigned long long c = 0, k = 0;
+    host_batch_chunking(dtype, total, subsets_per_lane, &c, &k);
+    *hChunk = c;
+    *hChunks = k;
     return RADIC_OK;
 }
 

@@ -16,6 +16,18 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kPrefixBlock = 64;     // prefixes of m-2 columns per wave block (prefix-shared kernels)
 constexpr int kGroupBlock = 16;      // prefixes of m-3 columns per wave block (group-shared kernel)
+// Colex blocks of a whole rank space (prefix-shared kernels): about this many
+// minors per block, so that the heaviest prefixes do not make one block the
+// whole launch's critical path.
+constexpr unsigned kColexPairs = 2048;
+
+// Prefixes per colex block for prefixes with r later columns (C(r, 2) minors
+// each): about K minors, between 1 and kPrefixBlock prefixes.
+__host__ __device__ inline int colex_run(int r, unsigned K) {
+    const unsigned pairs = (unsigned)(r * (r - 1) / 2);
+    const unsigned k = pairs ? K / pairs : (unsigned)kPrefixBlock;
+    return k < 1u ? 1 : (k > (unsigned)kPrefixBlock ? kPrefixBlock : (int)k);
+}
 // FP32-bulk in the shared kernels: up to m = 8 a workgroup refactors its
 // flagged minors in double when its waves are done (eight lanes per minor, one
 // row each); above, the refactorisation kernel does it.
@@ -23,6 +35,12 @@ __host__ __device__ constexpr bool shared_tail_refactor(int m) { return m <= 8; 
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
 constexpr int kDeferEntries = 1 << 22;   // 16-byte deferral entries in a single-matrix workspace
+// FP32-bulk keeps a float result only over at least this many minors: a float
+// minor carries a relative error up to about u_f times its condition, which
+// the tolerance on the sum (relative to sum |det|) absorbs only when many
+// minors with independent rounding are added.  A call (or a batch matrix) with
+// fewer minors refactors every minor in double (threshold tau = +inf).
+constexpr unsigned long long kF32MinMinors = 4096;
 
 // Per-workgroup partial of a floating-point enumeration (32 bytes).
 struct Partial {
@@ -72,15 +90,14 @@ struct FloatJob {
     unsigned long long n_prefix;  // C(n-2, m-2) (mapping 1) or C(n-3, m-3) (mapping 2)
     unsigned long long p_begin;   // prefixes [p_begin, p_end) cover [q_begin, q_begin + count)
     unsigned long long p_end;
-    // Mapping 1: the prefix block that the i-th block slot of the launch takes
-    // (heaviest first), or null for blocks in dictionary order.
-    const unsigned* block_order;
+    // Mapping 1 over the whole rank space: 1 when the blocks are colex blocks
+    // (consecutive prefixes in colex order, last column first, about
+    // colex_pairs minors each, heaviest first; colex_blocks of them), 0 when
+    // block blk holds the prefixes p_begin + blk*64 ... in dictionary order.
+    int colex;
+    unsigned colex_pairs;
+    unsigned long long colex_blocks;
 };
-
-// The prefix block behind block slot blk of a launch.
-__device__ __forceinline__ unsigned long long prefix_block(const FloatJob& J, unsigned long long blk) {
-    return J.block_order ? (unsigned long long)J.block_order[blk] : blk;
-}
 
 // ---------------------------------------------------------------- timed launches
 // Start and stop events for the next launch_timed call on this thread: they

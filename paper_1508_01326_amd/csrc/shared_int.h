@@ -117,8 +117,10 @@ __device__ __forceinline__ void int_left_steps(double (&L)[M][P], double (&u)[P]
 // per lane; while their later columns fit the cap projected-column slots);
 // n_prefix = C(n-2, m-2) numbers all prefixes.  incl holds 2 x 64 scans (pairs,
 // then projected columns).  bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform
-// control flow outside the lanes' own walks.
-template <int M>
+// control flow outside the lanes' own walks.  COLEX: next and pi1 are colex
+// prefix numbers (unrank_prefix_colex) and the whole rank space is summed, so
+// no pair is clipped and rbase, R0, R1 are not used.
+template <int M, bool COLEX = false>
 __device__ void int_prefix_range(const double* cr, int n, const unsigned long long* bt, int bstride,
                                  unsigned long long next, unsigned long long pi1, unsigned long long n_prefix,
                                  unsigned long long rbase,
@@ -126,33 +128,36 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
                                  IntSlot* slot, unsigned* incl, double2* tv, int lane, double& acc) {
     constexpr int P = M - 2;
     constexpr int ST = IntLayout<M>::st;
-    while (next < pi1 && rbase < R1) {
+    while (next < pi1 && (COLEX || rbase < R1)) {
         // lane l takes prefix next + l if it starts before R1 and its later
         // columns still fit the projected-column slots (lane 0 always does)
         const unsigned long long pi = next + lane;
         const bool inb = pi < pi1;
         int c[P];
-        unrank_prefix<P>(inb ? pi : next, n, n_prefix, bt, bstride, c);
+        if (COLEX) unrank_prefix_colex<P>(inb ? pi : next, n, bt, bstride, c);
+        else unrank_prefix<P>(inb ? pi : next, n, n_prefix, bt, bstride, c);
         const int r = n - 1 - c[P - 1];
         const unsigned cfull = inb ? (unsigned)(r * (r - 1) / 2) : 0u;
         const unsigned cscan = wave_scan_u32(cfull, lane);
         const unsigned long long base = rbase + (cscan - cfull);
-        const bool have = inb && base < R1;
+        const bool have = inb && (COLEX || base < R1);
         const unsigned rs = wave_scan_u32(have ? (unsigned)r : 0u, lane);
         const bool take = have && rs <= (unsigned)cap;
         const int ntake = __popcll(__ballot(take));
         const unsigned round_total = __shfl(cscan, ntake - 1, kWave);
         const unsigned cnt = take ? cfull : 0u;
         unsigned lo_c = 0, hi_c = cnt;
-        if (base < R0) {
-            const unsigned long long d = R0 - base;
-            lo_c = d < cnt ? (unsigned)d : cnt;
+        if (!COLEX) {
+            if (base < R0) {
+                const unsigned long long d = R0 - base;
+                lo_c = d < cnt ? (unsigned)d : cnt;
+            }
+            if (base + cnt > R1) {
+                const unsigned long long d = R1 > base ? R1 - base : 0ull;
+                hi_c = d < cnt ? (unsigned)d : cnt;
+            }
+            if (hi_c < lo_c) hi_c = lo_c;
         }
-        if (base + cnt > R1) {
-            const unsigned long long d = R1 > base ? R1 - base : 0ull;
-            hi_c = d < cnt ? (unsigned)d : cnt;
-        }
-        if (hi_c < lo_c) hi_c = lo_c;
         const unsigned cc = hi_c - lo_c;
         const unsigned ccincl = wave_scan_u32(cc, lane);
         const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);

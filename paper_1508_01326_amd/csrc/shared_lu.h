@@ -101,10 +101,42 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
 }
 
 
+// Every rank of [lo, hi) factored in double by the wave's eight groups of eight
+// lanes (group_refactor_cols_f64: one row per lane, no per-lane matrix): group g
+// takes the g-th of 8 contiguous sub-ranges, unranks its first sequence
+// (Section 4) and walks the rest with the successor (Section 5); its first lane
+// adds the terms.  bt[x*BS + y] = C(x, y).  Counts the ranks in nvalid.
+template <int M, int BS, int S64>
+__device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
+                                     unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
+                                     double& ab, unsigned long long& nvalid) {
+    if (hi <= lo) return;
+    const int g = lane >> 3;
+    const unsigned long long per = (hi - lo + 7) / 8;
+    const unsigned long long s0 = lo + (unsigned long long)g * per;
+    const unsigned long long s1 = s0 + per < hi ? s0 + per : hi;
+    int col[M];
+    unrank_strided<M>(s0 < hi ? s0 : lo, J.n, bt, BS, col);
+    for (unsigned long long s = 0; s < per; ++s) {
+        double ad;
+        const double term = group_refactor_cols_f64<M, S64>(cd, col, lane, ad);
+        if (s0 + s < s1 && (lane & 7) == 0) {
+            double sum, err;
+            two_sum(h, term, sum, err);
+            h = sum;
+            l += err;
+            ab += ad;
+            nvalid += 1;
+        }
+        successor<M>(col, J.n);
+    }
+}
+
 // FP32-bulk tail of a prefix-shared workgroup.  Each wave queued its flagged
 // minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
 // segment overflowed drops its float sums and redoes its own blocks (BLOCK
-// prefixes of m-KT columns: gwave, gwave + nwaves, ...) in double.  The entries
+// prefixes of m-KT columns: gwave, gwave + nwaves, ...; colex blocks prefix by
+// prefix) in double, eight lanes per minor.  The entries
 // of the other waves are pooled and refactored in double by groups of eight
 // threads of the workgroup, in a fixed order (group g takes entries g, g + G, ...;
 // its first lane adds the term).  segn: a workgroup LDS
@@ -120,10 +152,20 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
     if (gcount > J.defer_cap) {
         hi = lo = ab = 0.0;
         nfb = 0;
+        // one contiguous rank range per step: a dictionary block whole, a colex
+        // block prefix by prefix (one call site keeps the registers of this cold
+        // path within those of the main loop)
+        const bool colex = KT == 2 && J.colex;
         for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
-            unsigned long long r0, r1;
-            prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, prefix_block(J, blk), r0, r1, BS);
-            redo_ranks_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+            unsigned long long t0 = 0;
+            int segs = 1;
+            if (colex) colex_block<M - 2>(blk, J.n, bt, BS, J.colex_pairs, lane, t0, segs);
+            for (int sgm = 0; sgm < segs; ++sgm) {
+                unsigned long long r0, r1;
+                if (colex) colex_prefix_ranks<M, BS>(J, bt, t0 + (unsigned long long)sgm, r0, r1);
+                else prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
+                redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+            }
         }
     }
     unsigned E = 0;

@@ -189,3 +189,26 @@ def test_tune_table_roundtrip(tmp_path):
         radic.tune_load(bad)
     with pytest.raises(radic.RadicError):
         radic.tune_load(tmp_path / "missing.txt")
+
+
+def test_batch_chunking_bounds():
+    # every chunk is a multiple of 64 ranks and at least 64 * spl; chunks cover the
+    # rank space exactly once; float matrices have at most 256 chunks, int32 at
+    # most 2^16, so a class queue over 2^24 matrices stays far below 2^63 and its
+    # 64-bit counter cannot wrap
+    for dtype in (0, 1):
+        for m, n in [(1, 1), (2, 24), (10, 24), (6, 40), (12, 64), (11, 64), (3, 64), (10, 64)]:
+            for spl in (1, 4, 8, 64):
+                chunk, k = radic.host_batch_chunking(dtype, m, n, spl)
+                total = math.comb(n, m)
+                assert chunk % 64 == 0 and chunk >= 64 * spl
+                assert (k - 1) * chunk < total <= k * chunk
+                assert k <= (256 if dtype == 0 else 1 << 16)
+                assert k * (1 << 24) < 1 << 63
+    # the worst single int32 matrix the batched path accepts (m <= 12, n <= 64)
+    chunk, k = radic.host_batch_chunking(1, 12, 64, 1)
+    assert k <= 1 << 16 and chunk >= math.comb(64, 12) // (1 << 16)
+    with pytest.raises(radic.RadicError):
+        radic.host_batch_chunking(2, 3, 5, 1)
+    with pytest.raises(radic.RadicError):
+        radic.host_batch_chunking(0, 6, 5, 1)

@@ -129,24 +129,6 @@ def test_graph_replays():
         G.destroy()
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
-def test_workload5_sampled(precision):
-    batch = workloads.batch_matrices()
-    mats = [A for _, A in batch]
-    print(f"[case] workload5 4096 {precision}", flush=True)
-    res = radic.radic_det_batched(radic.Batch(mats), precision)
-    assert sum(r["n_subsets"] for r in res) == 342865835
-    assert all(r["status"] == 0 for r in res)
-    rng = np.random.default_rng(55)
-    small = [b for b, A in enumerate(mats) if math.comb(A.shape[1], A.shape[0]) <= 20000]
-    idx = list(rng.choice(small, size=48, replace=False))
-    # plus the largest matrix of each type
-    for kind in ("f64", "i32"):
-        cands = [b for b, (k, A) in enumerate(batch) if k == kind]
-        idx.append(max(cands, key=lambda b: math.comb(mats[b].shape[1], mats[b].shape[0])))
-    check(mats, res, precision, idx)
-
-
 def test_autotune_batched_and_int():
     print("[case] autotune batched", flush=True)
     spl, block = radic.autotune(radic.RADIC_WS_BATCHED, precision="fp32_bulk")

@@ -37,8 +37,9 @@ def run(A, precision, what, **kw):
     return radic.radic_det(to_device(A), precision=precision, **kw)
 
 
-SHAPES = [(3, 3), (3, 4), (3, 40), (3, 130), (4, 4), (4, 17), (5, 14), (5, 21), (6, 13), (6, 22), (7, 16),
-          (7, 19), (8, 8), (8, 17), (8, 21), (9, 18), (10, 10), (10, 16), (11, 15), (12, 12), (12, 16)]
+SHAPES = [(3, 3), (3, 4), (3, 40), (3, 130), (4, 4), (4, 17), (4, 20), (5, 14), (5, 21), (6, 13), (6, 22), (7, 16),
+          (7, 19), (8, 8), (8, 17), (8, 21), (9, 18), (10, 10), (10, 16), (11, 15), (11, 17), (12, 12), (12, 16),
+          (12, 17)]
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
@@ -180,8 +181,9 @@ def test_fallback_forced_everywhere():
 @pytest.mark.parametrize("m", [3, 4, 5, 6, 7, 8])
 def test_fallback_forced_each_m(m):
     # every minor refactored in double by the workgroup's tail, for each m it
-    # serves (eight lanes per minor, rows beyond m idle)
-    n = m + 7
+    # serves (eight lanes per minor, rows beyond m idle); n is the smallest with
+    # at least 4096 minors, below which FP32-bulk runs the double kernel
+    n = next(k for k in range(m, 200) if math.comb(k, m) >= 4096)
     A = workloads.random_float(m, n, seed=900 + m)
     ref = oracle.radic_f64(A)
     radic.set_fallback_tau(float("inf"))

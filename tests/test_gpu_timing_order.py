@@ -1,10 +1,12 @@
 """GPU tests of two pieces around the enumeration kernels: the library's timing
-hook (HIP events bound to the main kernel's dispatch) and the heaviest-first
-order in which whole-matrix prefix-shared launches take their blocks.
+hook (HIP events bound to the main kernel's dispatch) and the order in which
+whole-matrix prefix-shared launches take their blocks (colex order of the
+prefixes, heaviest first, computed by the kernel itself).
 
 Timing must not change what is computed; the block order must give the same
-bits on every call of a shape and results that agree with the oracle and with
-range calls (which keep dictionary order).
+bits on every call of a shape, eager or replayed from a captured graph (even
+when the capture is the shape's first call), and results that agree with the
+oracle and with range calls (which keep dictionary order).
 
 Every case prints its identity before the GPU call so a failing run names it."""
 import math
@@ -101,3 +103,40 @@ def test_block_order_exact_reproducible():
     ref = oracle.radic_int(A)
     assert radic.radic_det_int_exact(dA) == ref
     assert radic.radic_det_int_exact(dA) == ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+def test_first_call_of_a_shape_captured(precision):
+    # the first call of a shape goes into a HIP graph: it needs no allocation,
+    # no host synchronisation and no table, and every replay gives the bits of
+    # an eager call
+    import torch
+    from paper_1508_01326_amd import binding
+    print("[case] device set-up call 3x9", flush=True)
+    radic.radic_det(to_device(workloads.random_float(3, 9, seed=8400)))
+    m, n = (7, 23) if precision == "fp64" else (7, 25)
+    A = workloads.random_float(m, n, seed=8401 + n)
+    dA = to_device(A)
+    out = binding.new_f64_result()
+    work = binding.workspace(radic.RADIC_WS_DET, m, n)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    print(f"[case] capture first call {m}x{n} {precision}", flush=True)
+    with torch.cuda.graph(g, stream=side):
+        radic.radic_det(dA, precision=precision, out=out, work=work, sync=False)
+    replays = []
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        print(f"[case] replay {rep}", flush=True)
+        g.replay()
+        torch.cuda.synchronize()
+        replays.append(binding.read_f64_result(out))
+        _ = (torch.ones(1000, device="cuda") * 2).sum().item()   # eager work between replays
+    eager = radic.radic_det(dA, precision=precision)
+    for r in replays:
+        assert bits(r) == bits(eager)
+    ref = oracle.radic_f64(A)
+    assert_close(eager["value"], ref["value"], normaliser(ref["abs_sum"], A), TOL[precision], "captured shape")
+    del g
