@@ -254,6 +254,27 @@ int radic_det_batched(const radic_matrix_desc *dDesc, int batch, const double *d
                       size_t work_bytes, hipStream_t stream);
 
 /*
+ * radic_det_batched_noalloc -- radic_det_batched for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results as
+ * radic_det_batched, without dWork/work_bytes: the workspace is a static
+ * device array of the library (36 MiB, held on every device the library runs
+ * on until the process ends), sized for at most 4096 matrices.
+ *   batch > 4096 -> RADIC_ENOTSUP (radic_last_error says why); nothing enqueued.
+ * Allocates nothing (no hipMalloc, no allocating library call; the timing hook
+ * of radic_profile_enable does not time it).  The first call on a device takes
+ * the array's address with hipGetSymbolAddress and uploads the library's
+ * tables, like any first call: make it outside stream capture.
+ * All calls on one device share that device's array, and every kernel of a
+ * call rewrites what it reads (no state is carried between calls), but calls
+ * that may overlap on one device (other streams, other threads) race on it.
+ * Asynchronous.
+ */
+int radic_det_batched_noalloc(const radic_matrix_desc *dDesc, int batch, const double *dF64,
+                              const int32_t *dI32, int prec, radic_batch_result *dOut,
+                              hipStream_t stream);
+
+/*
  * Captured launch of radic_det_batched: records the same work into a HIP graph
  * once and replays it with a single launch.  *hGraph receives an opaque handle.
  * Arguments are bound at creation; replaying reuses them (contents of the

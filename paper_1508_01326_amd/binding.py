@@ -70,6 +70,7 @@ SIGNATURES = {
     "radic_det_subsets": (_i, [_vp, _i, _i, _i64, _i, _u64, _u64, _vp, _vp, _vp]),
     "radic_det_int_exact": (_i, [_vp, _i, _i, _i64, _u32p, _i, _ip, _ip, _vp, _sz, _vp]),
     "radic_det_batched": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _sz, _vp]),
+    "radic_det_batched_noalloc": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp]),
     "radic_batched_graph_create": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _sz, ctypes.POINTER(_vp)]),
     "radic_graph_launch": (_i, [_vp, _vp]),
     "radic_graph_destroy": (_i, [_vp]),
@@ -363,7 +364,7 @@ def host_batch_chunking(dtype, m, n, subsets_per_lane):
 class Batch:
     """Device buffers for radic_det_batched: entry pools, descriptors, results and
     workspace, built from a list of 2-D numpy arrays (float64 or int32).  With
-    work=False no workspace is made."""
+    work=False no workspace is made (for radic_det_batched_noalloc)."""
 
     def __init__(self, matrices, device="cuda", work=True):
         torch = _torch()
@@ -416,6 +417,21 @@ def radic_det_batched(batch, precision="fp64", stream=None, sync=True):
     torch = _torch()
     rc = lib().radic_det_batched(*batch.args(precision), _stream_handle(stream))
     _check(rc, "radic_det_batched")
+    if not sync:
+        return None
+    torch.cuda.synchronize()
+    return batch.results()
+
+
+def radic_det_batched_noalloc(batch, precision="fp64", stream=None, sync=True):
+    """Run radic_det_batched_noalloc on a Batch (its workspace, if any, is not
+    used: the library's static scratch is); returns the per-matrix results."""
+    torch = _torch()
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    rc = lib().radic_det_batched_noalloc(ctypes.c_void_p(batch.desc.data_ptr()), batch.batch,
+                                         ctypes.c_void_p(batch.f64.data_ptr()), ctypes.c_void_p(batch.i32.data_ptr()),
+                                         prec, ctypes.c_void_p(batch.out.data_ptr()), _stream_handle(stream))
+    _check(rc, "radic_det_batched_noalloc")
     if not sync:
         return None
     torch.cuda.synchronize()

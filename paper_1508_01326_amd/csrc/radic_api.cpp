@@ -98,6 +98,18 @@ static int host_error(int status, const char* what) {
     return status;
 }
 
+// ---------------------------------------------------------------- static scratch
+// The workspace of radic_det_batched_noalloc: a file-scope device array, so
+// that the call allocates nothing.  Every device the library runs on holds its
+// own copy until the process ends.  In host code `scratch` names a host-side
+// stand-in, not device memory: its device address is taken once per device at
+// set-up (ensure_device, with that device current) and only that address is
+// used.  Sized for kScratchBatch matrices of the batched layout (checked at
+// set-up).
+constexpr int kScratchBatch = 4096;
+constexpr size_t kScratchBytes = (size_t)36 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void* g_scratch[64];   // per device: the address of that device's scratch
 
 // ---------------------------------------------------------------- primes of the exact path
 // Deterministic Miller-Rabin: bases 2, 3, 5, 7 decide every n < 3,215,031,751.
@@ -186,6 +198,14 @@ static int ensure_device(int* lds_limit = nullptr) {
     if (ue == hipSuccess) ue = upload_binomials_shared3(t.data());
     if (ue == hipSuccess) ue = upload_binomials_wide(t.data());
     if (ue != hipSuccess) return device_error("upload of the binomial table", ue);
+    if (batched_workspace_bytes(kScratchBatch) > kScratchBytes)
+        return host_error(RADIC_ENOTSUP, "static scratch smaller than the batched layout needs");
+    void* sp = nullptr;
+    const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+    if (se != hipSuccess) return device_error("hipGetSymbolAddress of the static scratch", se);
+    if (sp == nullptr || (reinterpret_cast<uintptr_t>(sp) & 255u))
+        return host_error(RADIC_EDEVICE, "static scratch address missing or misaligned");
+    g_scratch[dev] = sp;
     g_dev_ready[dev] = true;
     return RADIC_OK;
 }
@@ -828,8 +848,9 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     return RADIC_OK;
 }
 
-// The batched launch sequence on a workspace that has been checked; `timed`
-// lets the timing hook time it.
+// The batched launch sequence on a workspace that has been checked; shared by
+// radic_det_batched (caller's workspace) and radic_det_batched_noalloc (the
+// device's static scratch).
 static int batched_launch(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32,
                           int prec, radic_batch_result* dOut, void* dWork, hipStream_t stream, bool timed) {
     const Shape sf = pick_shape(RADIC_WS_BATCHED, prec, 0, 0);
@@ -863,6 +884,25 @@ int radic_det_batched(const radic_matrix_desc* dDesc, int batch, const double* d
     if (rc != RADIC_OK) return rc;
     if ((rc = ensure_device()) != RADIC_OK) return rc;
     return batched_launch(dDesc, batch, dF64, dI32, prec, dOut, dWork, stream, true);
+}
+
+int radic_det_batched_noalloc(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32,
+                              int prec, radic_batch_result* dOut, hipStream_t stream) {
+    if (!dDesc || !dOut || batch < 0) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (batch == 0) return RADIC_OK;
+    if (batch > kScratchBatch)
+        return host_error(RADIC_ENOTSUP, "radic_det_batched_noalloc: more matrices than the static scratch holds "
+                                         "(at most 4096)");
+    int rc = ensure_device();
+    if (rc != RADIC_OK) return rc;
+    int dev = 0;
+    const hipError_t ge = hipGetDevice(&dev);
+    if (ge != hipSuccess) return device_error("hipGetDevice", ge);
+    void* ws = g_scratch[dev];   // set by ensure_device for this device
+    if (!ws) return host_error(RADIC_EDEVICE, "static scratch not set up on this device");
+    // the timing hook is not used here: it may create HIP events
+    return batched_launch(dDesc, batch, dF64, dI32, prec, dOut, ws, stream, false);
 }
 
 struct GraphHandle {
