@@ -222,13 +222,13 @@ def other_workloads(radic, binding, workloads, torch, dev, args):
         r = call()
         ms = timed_calls(call, 3, torch)
         kms = kernel_ms(radic, call, 2)
-        enum = "per_minor" if p == "fp64" else "auto"      # FP64 prefix sharing stops at m = 10
+        enum = "auto"
         xf = executed_flops(12, 36, enum)
         peak = PEAK_FP64_TFLOPS if p == "fp64" else PEAK_FP32_TFLOPS
         res[p] = {"ms_per_call": ms, "subdet_per_s": total / (ms * 1e-3),
                   "err_over_sum_abs_vs_exact": abs(r["value"] - ex) / S, "tol": 1e-12 if p == "fp64" else 1e-5,
                   "n_fallback": r["n_fallback"], "fallback_fraction": r["n_fallback"] / total,
-                  "kernel": ("k_radic_float<12,false,false,false>" if p == "fp64" else "k_radic_shared<12,true>"),
+                  "kernel": "k_radic_shared<12,%s>" % ("false" if p == "fp64" else "true"),
                   "kernel_ms": kms,
                   "roofline": {"bound": "alu", "achieved": xf / (kms * 1e-3) / 1e12, "peak": peak, "unit": "TFLOP/s",
                                "frac": xf / (kms * 1e-3) / 1e12 / peak,
@@ -360,10 +360,13 @@ def main():
           flush=True)
 
     if args.copy_bytes > 0:
+        # a copy kernel that reads and writes copy_bytes each (an element-wise
+        # multiply by one: a same-device copy_ may go to a DMA engine, which the
+        # kernel counters do not see)
         src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         print(f"[bench] reference copy of {src.numel() * 4} bytes done", file=sys.stderr, flush=True)
         del src, dst

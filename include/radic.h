@@ -319,15 +319,14 @@ int radic_set_fallback_tau(double tau);
  *                             LU with partial pivoting, whose pivots and
  *                             multipliers depend on those columns only; each
  *                             minor then costs its last two elimination steps.
- *                             Used for 3 <= m <= 10 (FP64) or m <= 12
- *                             (FP32_BULK); other shapes fall back to per-minor.
+ *                             Used for 3 <= m <= 12; other shapes fall back
+ *                             to per-minor.
  *  RADIC_ENUM_GROUP_SHARED    the minors sharing their first m-3 columns share
  *                             those m-3 steps; each minor then costs the
  *                             determinant of its last 3 x 3 block, a dot
  *                             product with a cross product formed once per
  *                             pair of its last three columns.  Used for
- *                             4 <= m <= 10 (FP64) or m <= 12 (FP32_BULK); m = 3
- *                             falls back to prefix-shared.
+ *                             4 <= m <= 12; m = 3 falls back to prefix-shared.
  * RADIC_ENUM_AUTO takes prefix-shared where supported.  All give every minor's
  * determinant (the terms of eq. (1)) individually; they differ in rounding only.
  * radic_det_subsets always uses per-minor.  The same switch applies to

@@ -409,6 +409,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared3(FloatJob J) {
             if (F32 && gcount > J.defer_cap) overflow = true;
             next += (unsigned long long)ntake;
             wave_lds_sync();
+            if constexpr (F32 && shared_tail_refactor(M)) {
+                if (!overflow) relieve_segment<M, S64>(J, cd, gwave, gcount, lane, hi, lo, ab);
+            }
         }
     }
     if constexpr (F32 && shared_tail_refactor(M)) {

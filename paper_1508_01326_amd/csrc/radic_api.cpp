@@ -229,7 +229,9 @@ static Shape default_shape(int kind, int prec, int m, int n) {
     (void)n;
     Shape s{8, 256};
     if (kind == RADIC_WS_BATCHED) {
-        s.spl = prec == 2 ? 4 : 8;   // prec 2: the exact kernel
+        // chunks of at least 64 * 32 ranks: measured on the 4096-matrix batch
+        // (62.0 / 51.2 / 47.5 / 46.6 / 49.1 / 55.1 ms at spl 4 / 8 / 16 / 32 / 64 / 128)
+        s.spl = 32;
         return s;
     }
     if (m <= 3) s.spl = 32;
@@ -449,10 +451,10 @@ static unsigned long long host_prefix_index(int m, int n, unsigned long long q, 
 
 // The float enumeration of a call: 0 per-minor, 2 prefix-shared (minors with
 // equal first m-2 columns share those LU steps), 3 group-shared (equal first
-// m-3 columns).  The shared kernels cover 3 <= m <= 12 (group-shared from
-// m = 4); FP64 stops at 10, where the prefix block no longer fits the register
-// file.  The automatic choice is prefix-shared (measured at least as fast as
-// group-shared on the 8 x 32 workload).
+// m-3 columns).  The shared kernels cover 3 <= m <= 12 in both precisions
+// (group-shared from m = 4).  The automatic choice is prefix-shared (measured
+// at least as fast as group-shared on the 8 x 32 workload, and faster than the
+// per-minor kernel at every m it covers).
 static int float_enumeration(int m, int n, int prec) {
     int mode;
     {
@@ -460,7 +462,7 @@ static int float_enumeration(int m, int n, int prec) {
         mode = g_enumeration;
     }
     if (mode == RADIC_ENUM_PER_MINOR) return 0;
-    const bool ok2 = m >= 3 && (prec == RADIC_FP32_BULK ? m <= 12 : m <= 10);
+    const bool ok2 = m >= 3 && m <= 12;
     const bool ok3 = ok2 && m >= 4;
     if (mode == RADIC_ENUM_GROUP_SHARED) return ok3 ? 3 : (ok2 ? 2 : 0);
     return ok2 ? 2 : 0;

@@ -132,6 +132,40 @@ __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long
     }
 }
 
+// FP32-bulk, m <= 8, between two rounds of a prefix-shared wave: when the wave's
+// segment of J.fb_entries is more than half full (gcount entries, wave-uniform),
+// the wave refactors them in double here, in whole passes of its eight groups of
+// eight lanes (group g takes entries g, g + 8, ...; its first lane adds the
+// term), and moves the at most seven left to the front of the segment; gcount
+// becomes their number.  This keeps a wave that meets many flagged minors from
+// overflowing its segment (and redoing its blocks in double).  Every lane calls
+// this.
+template <int M, int S64>
+__device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned long long gwave, int& gcount, int lane,
+                                double& hi, double& lo, double& ab) {
+    if (2 * gcount <= J.defer_cap) return;
+    const int F = gcount & ~7;
+    uint4* seg = reinterpret_cast<uint4*>(J.fb_entries) + (size_t)gwave * J.defer_cap;
+    __threadfence_block();   // the entries other lanes of the wave stored
+    for (int e = lane >> 3; e < F; e += 8) {
+        double ad;
+        const double term = group_refactor_f64<M, S64>(cd, reinterpret_cast<const unsigned*>(seg + e), lane, ad);
+        if ((lane & 7) == 0) {
+            double sum, err;
+            two_sum(hi, term, sum, err);
+            hi = sum;
+            lo += err;
+            ab += ad;
+        }
+    }
+    // entries [F, gcount) to [0, gcount - F): disjoint, since gcount - F < 8 <= F
+    const int rest = gcount - F;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (lane < rest) v = seg[F + lane];
+    if (lane < rest) seg[lane] = v;
+    gcount = rest;
+}
+
 // FP32-bulk tail of a prefix-shared workgroup.  Each wave queued its flagged
 // minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
 // segment overflowed drops its float sums and redoes its own blocks (BLOCK

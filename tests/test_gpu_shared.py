@@ -238,10 +238,6 @@ def test_workload4_sampled_ranges(mode):
     for q0 in (0, total // 3 + 12345, total - 50000):
         part = oracle.radic_f64(A, q0=q0, count=50000)
         for prec in ("fp64", "fp32_bulk"):
-            if prec == "fp64":
-                radic.set_enumeration("auto")   # FP64 m = 12 runs per-minor
-            else:
-                radic.set_enumeration(mode)
             print(f"[case] workload4 window {q0} {prec}", flush=True)
             r = radic.radic_det_range(to_device(A), q0, 50000, precision=prec)
             assert r["n_subsets"] == 50000
