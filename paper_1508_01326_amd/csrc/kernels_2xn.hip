@@ -85,7 +85,7 @@ __global__ __launch_bounds__(256) void k_2xn_runs(const double* A, long long lda
     for (long long j = t0; j < t1; ++j) {
         const double sg = (j & 1) ? 1.0 : -1.0;   // (-1)^(j+1) for the 0-based column j
         const double a1 = A[j], a2 = A[lda + j];
-        bad |= !isfinite(a1) | !isfinite(a2);
+        bad |= (!isfinite(a1) || !isfinite(a2)) ? 1 : 0;
         const double u = sg * a1, v = sg * a2;
         // appending column j: C += U v - V u, B += Ua |v| + Va |u|
         r.C = dd_plus(r.C, dd_plus(dd_mul(r.U, dd(v)), dd_neg(dd_mul(r.V, dd(u)))));

@@ -21,10 +21,12 @@
 #include "lu_float.h"
 #include "modp.h"
 #include "shared_int.h"
+#include "shared_int3.h"
 
 namespace radic {
 
 constexpr int kBatchMaxN = 64;           // widest matrix a wave stages in LDS
+static_assert(kBatchMaxN <= kWave, "the setup kernel reads one column per lane");
 constexpr int kBatchWaves = 4;           // waves per workgroup of the persistent kernels
 
 struct BatchMeta {
@@ -104,14 +106,17 @@ __host__ __device__ inline size_t batch_ws_bytes(int batch) {
 }
 
 // ---------------------------------------------------------------- setup
+// One wave per matrix: its lanes read the matrix together (lane j column j, for
+// j < n), and the wave reduces what the matrix's meta needs.
 __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int b = blockIdx.x * (blockDim.x / kWave) + wave;
     if (b >= J.batch) return;
     const radic_matrix_desc d = J.desc[b];
     BatchMeta mt{};
     mt.kind = -1;
     mt.status = RADIC_OK;
-    for (int i = 0; i < RADIC_MAX_PRIMES; ++i) J.residues[(size_t)b * RADIC_MAX_PRIMES + i] = 0ull;
+    if (lane < RADIC_MAX_PRIMES) J.residues[(size_t)b * RADIC_MAX_PRIMES + lane] = 0ull;
     const bool bad_dtype = d.dtype != 0 && d.dtype != 1;
     const bool no_pool = (d.dtype == 0 && !J.f64) || (d.dtype == 1 && !J.i32);
     if (d.m < 1 || d.n < 1 || d.lda < d.n || d.offset < 0 || bad_dtype || no_pool) {
@@ -122,6 +127,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
         mt.status = RADIC_ENOTSUP;
     } else {
         const unsigned long long total = g_binom[d.n * kBinomCols + d.m];
+        const bool col = lane < d.n;   // kBatchMaxN <= 64: one column per lane
         if (total >= (1ull << 63)) {
             mt.status = RADIC_EOVERFLOW;
         } else if (d.dtype == 0) {
@@ -129,40 +135,47 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
             mt.total = total;
             batch_chunking(0, total, J.spl_float, mt.chunk, mt.nchunks);
             const double* A = J.f64 + d.offset;
-            int se = 0, bad = 0;
+            int se = 0;
+            bool bad = false;
             for (int i = 0; i < d.m; ++i) {
-                double mx = 0.0;
-                for (int j = 0; j < d.n; ++j) {
-                    const double v = A[(long long)i * d.lda + j];
-                    bad |= !isfinite(v);
-                    mx = fmax(mx, fabs(v));
-                }
+                const double v = col ? A[(long long)i * d.lda + lane] : 0.0;
+                bad |= !isfinite(v);
+                double mx = fabs(v);
+#pragma unroll
+                for (int o = kWave / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
                 int e = 0;
                 if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e);
                 se += e;
             }
             mt.scale_exp = J.prec == RADIC_FP32_BULK ? se : 0;
             mt.all_double = J.prec == RADIC_FP32_BULK && total < kF32MinMinors;
-            if (bad) {
+            if (__ballot(bad)) {
                 mt.status = RADIC_ENONFINITE;
                 mt.kind = -1;
             }
         } else {
             // exact: primes for the bound e_m(column norms) (Hadamard per minor)
             const int* A = J.i32 + d.offset;
+            double s = 0.0;
+            for (int i = 0; i < d.m; ++i) {
+                const double a = col ? (double)A[(long long)i * d.lda + lane] : 0.0;
+                s = __builtin_fma(a, a, s);
+            }
+            const double xl = sqrt(s) * (1.0 + 1e-12);
             double e[RADIC_MAX_M + 1];
             e[0] = 1.0;
-            for (int k = 1; k <= d.m; ++k) e[k] = 0.0;
-            for (int j = 0; j < d.n; ++j) {
-                double s = 0.0;
-                for (int i = 0; i < d.m; ++i) {
-                    const double a = (double)A[(long long)i * d.lda + j];
-                    s = __builtin_fma(a, a, s);
-                }
-                const double x = sqrt(s) * (1.0 + 1e-12);
-                for (int k = d.m; k >= 1; --k) e[k] = __builtin_fma(x, e[k - 1], e[k]);
+#pragma unroll
+            for (int k = 1; k <= RADIC_MAX_M; ++k) e[k] = 0.0;
+            for (int j = 0; j < d.n; ++j) {   // every lane the same recurrence, column j's norm from lane j
+                const double x = __shfl(xl, j, kWave);
+#pragma unroll
+                for (int k = RADIC_MAX_M; k >= 1; --k)
+                    if (k <= d.m) e[k] = __builtin_fma(x, e[k - 1], e[k]);
             }
-            const double need = log2(e[d.m] * (1.0 + 1e-9) + 1.0) + 1.0 + 1e-6;
+            double em = 0.0;
+#pragma unroll
+            for (int k = 0; k <= RADIC_MAX_M; ++k) em = k == d.m ? e[k] : em;
+            const double need = log2(em * (1.0 + 1e-9) + 1.0) + 1.0 + 1e-6;
             double have = 0.0;
             int k = 0;
             while (k < J.prime_count && have <= need) have += log2(g_prime[k++]);
@@ -176,7 +189,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
             }
         }
     }
-    J.meta[b] = mt;
+    if (lane == 0) J.meta[b] = mt;
 }
 
 // One workgroup per class: prefix sums of the class's chunk counts in matrix
@@ -360,6 +373,9 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
     FloatWaveLds<M, F32>& L = lds[wave];
     constexpr int cls = M - 1;   // class_of(0, M)
     const unsigned long long total = J.header->chunks[cls];
+    // a wave numbered past the class's chunk count would find the queue drained:
+    // it leaves without contending for it
+    if ((unsigned long long)blockIdx.x * kBatchWaves + wave >= total) return;
     const unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
     int staged = -1;
     for (;;) {
@@ -378,13 +394,19 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
 }
 
 // ---------------------------------------------------------------- exact chunks
-constexpr int kBatchCap = 256;   // projected-column slots per wave (prefix-shared exact chunks)
+// Exact chunks share elimination steps: the minors of a prefix (first m-2
+// columns) for 3 <= m < kGroupExactMin, of a group (first m-3 columns) from
+// there to m = 10 (groups hold C(r, 3) minors against C(r, 2) per prefix).
+constexpr int kGroupExactMin = 7;
+// projected-column slots (16 bytes) per wave: enough for 64 prefixes or groups
+// of the narrow matrices a batch holds
+template <int M> constexpr int batch_cap() { return M >= kGroupExactMin ? 512 : 256; }
 
 template <int M> struct IntWaveLds {
     double cr[kBatchMaxN * IntLayout<M>::st];
     IntSlot slot[M >= 3 && M <= 10 ? kPrefixBlock : 1];
-    unsigned incl[M >= 3 && M <= 10 ? 2 * kPrefixBlock : 1];   // pair and column scans
-    double2 tv[M >= 3 && M <= 10 ? kBatchCap : 1];
+    unsigned incl[M >= 3 && M <= 10 ? 2 * kPrefixBlock : 1];   // minor and column scans
+    double2 tv[M >= 3 && M <= 10 ? batch_cap<M>() : 1];
 };
 
 template <int M>
@@ -394,7 +416,35 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
     const int n = d.n;
     (void)restage;   // residues are restaged per prime
     const int* A = J.i32 + d.offset;
-    if constexpr (M >= 3 && M <= 10) {
+    if constexpr (M >= kGroupExactMin && M <= 10) {
+        // group-shared: the chunk's ranks [R0, R1), groups from the one holding R0
+        const unsigned long long R0 = c * mt.chunk;
+        const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
+        PrefixSpace sp;
+        sp.n = n;
+        sp.total = mt.total;
+        sp.n_prefix = g_binom[(n - 3) * kBinomCols + (M - 3)];
+        const unsigned long long first = group_of_rank<M>(R0, n, bt, RADIC_MAX_M);
+        const unsigned long long rbase = first_completion_rank<M, PrefixSpace, 3>(first, sp, bt, RADIC_MAX_M);
+        for (int pi = 0; pi < mt.n_primes; ++pi) {
+            const double p = g_prime[pi], pinv = g_prime_inv[pi];
+            wave_lds_sync();
+            for (int e = lane; e < M * n; e += kWave) {
+                const int i = e / n, j = e - i * n;
+                const double v = (double)A[(long long)i * d.lda + j];
+                const double q = __builtin_floor(v * pinv);
+                L.cr[j * ST + i] = mod_fix(__builtin_fma(-q, p, v), p);
+            }
+            wave_lds_sync();
+            double acc = 0.0;
+            int_group_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, R0, R1, p, pinv,
+                               batch_cap<M>(), L.slot, L.incl, reinterpret_cast<uint4*>(L.tv), lane, acc);
+#pragma unroll
+            for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);
+            if (lane == 0) atomicAdd(&J.residues[(size_t)b * RADIC_MAX_PRIMES + pi], (unsigned long long)acc);
+        }
+        return;
+    } else if constexpr (M >= 3 && M <= 10) {
         // prefix-shared: the chunk's ranks [R0, R1), prefixes from the one holding R0
         const unsigned long long R0 = c * mt.chunk;
         const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
@@ -415,7 +465,7 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
             }
             wave_lds_sync();
             double acc = 0.0;
-            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, R0, R1, p, pinv, kBatchCap,
+            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, R0, R1, p, pinv, batch_cap<M>(),
                                 L.slot, L.incl, L.tv, lane, acc);
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);
@@ -479,6 +529,11 @@ __device__ __forceinline__ void batch_int_body(const BatchJob& J) {
     __shared__ IntWaveLds<M> lds[kBatchWaves];
     // binomial table C(x, y), x < kBatchMaxN, y < RADIC_MAX_M, for the prefix walk
     __shared__ unsigned long long bt[M >= 3 && M <= 10 ? kBatchMaxN * RADIC_MAX_M : 1];
+    constexpr int cls = RADIC_MAX_M + M - 1;   // class_of(1, M)
+    const unsigned long long total = J.header->chunks[cls];
+    // waves numbered past the class's chunk count would find the queue drained:
+    // a workgroup of only such waves leaves at once, the others after the barrier
+    if ((unsigned long long)blockIdx.x * kBatchWaves >= total) return;
     if constexpr (M >= 3 && M <= 10) {
         for (int e = threadIdx.x; e < kBatchMaxN * RADIC_MAX_M; e += blockDim.x) {
             const int x = e / RADIC_MAX_M, y = e - x * RADIC_MAX_M;
@@ -487,9 +542,8 @@ __device__ __forceinline__ void batch_int_body(const BatchJob& J) {
         __syncthreads();
     }
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    if ((unsigned long long)blockIdx.x * kBatchWaves + wave >= total) return;
     IntWaveLds<M>& L = lds[wave];
-    constexpr int cls = RADIC_MAX_M + M - 1;   // class_of(1, M)
-    const unsigned long long total = J.header->chunks[cls];
     const unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
     int staged = -1;
     for (;;) {
@@ -647,7 +701,7 @@ hipError_t launch_batched(const radic_matrix_desc* desc, int batch, const double
     J.partials = reinterpret_cast<Partial*>(w + off_partials(batch));
     J.residues = reinterpret_cast<unsigned long long*>(w + off_residues(batch));
     (void)hipGetLastError();
-    hipLaunchKernelGGL(k_batch_setup, dim3((batch + 255) / 256), dim3(256), 0, s, J);
+    hipLaunchKernelGGL(k_batch_setup, dim3((batch + 3) / 4), dim3(256), 0, s, J);
     hipLaunchKernelGGL(k_batch_scan, dim3(kClasses), dim3(1024), 0, s, J);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
