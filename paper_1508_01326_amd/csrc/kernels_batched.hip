@@ -22,6 +22,7 @@
 #include "modp.h"
 #include "shared_int.h"
 #include "shared_int3.h"
+#include "shared_round.h"
 
 namespace radic {
 
@@ -366,16 +367,169 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
     out = Partial{hi, lo, ab, nfb};
 }
 
+// ---------------------------------------------------------------- float chunks, prefix-shared (m >= 3)
+// From m = 3 a float chunk runs the prefix-shared round of the single-matrix
+// kernels over its rank window: the minors of a prefix (first m-2 columns)
+// share its elimination steps and end with a 2 x 2 determinant.  FP32-bulk
+// queues its flagged minors in the wave's LDS and refactors them in double by
+// lane groups (between rounds once the queue is half full, and at the end of
+// the chunk); a round whose flagged minors would not fit is done again in
+// double.  Matrices with fewer than kF32MinMinors minors run the double round.
+constexpr int kBatchSharedCap = 256;   // projected-column slots per wave
+constexpr int kBatchDefer = 128;       // FP32-bulk queue entries per wave
+constexpr int kBatchBS = RADIC_MAX_M + 1;   // stride of the float kernels' binomial table (C(x, y), y <= m)
+
+template <int M, bool F32> struct FloatSharedLds {
+    double cd[kBatchMaxN * SharedLayout<M>::s64];   // (row-scaled for FP32-bulk) double copy
+    float cf[F32 ? kBatchMaxN * SharedLayout<M>::s32 : 1];   // float copy, reciprocal column scale in slot m
+    alignas(16) unsigned char rec[kHdrBytes + kScanBytes + (F32 ? kF32Extra : 0)];
+    uint4 tv[kBatchSharedCap];
+    uint4 queue[F32 ? kBatchDefer : 1];
+    int rowexp[M];
+};
+
+// Stage matrix d into the wave's copies, with the layout and scaling of the
+// single-matrix prefix-shared kernels: FP32-bulk rows scaled by 2^-e_i (e_i the
+// exponent of the row maximum), the float copy, and its reciprocal column
+// scales.
+template <int M, bool F32>
+__device__ void stage_float_shared(const BatchJob& J, const radic_matrix_desc& d, FloatSharedLds<M, F32>& L,
+                                   int lane) {
+    constexpr int S64 = SharedLayout<M>::s64, S32 = SharedLayout<M>::s32;
+    const double* A = J.f64 + d.offset;
+    const int n = d.n;
+    wave_lds_sync();
+    if (F32 && lane < M) {
+        double mx = 0.0;
+        for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(A[(long long)lane * d.lda + j]));
+        int e_row = 0;
+        if (mx > 0.0 && isfinite(mx)) (void)frexp(mx, &e_row);
+        L.rowexp[lane] = e_row;
+    }
+    wave_lds_sync();
+    for (int e = lane; e < M * n; e += kWave) {
+        const int i = e / n, j = e - i * n;
+        double v = A[(long long)i * d.lda + j];
+        if (F32) v = ldexp(v, -L.rowexp[i]);
+        L.cd[j * S64 + i] = v;
+        if (F32) L.cf[j * S32 + i] = (float)v;
+    }
+    wave_lds_sync();
+    if (F32) {
+        for (int j = lane; j < n; j += kWave) {
+            float sc = 0.f;
+#pragma unroll
+            for (int i = 0; i < M; ++i) sc = fmaxf(sc, fabsf(L.cf[j * S32 + i]));
+            L.cf[j * S32 + M] = sc > 0.f ? 1.0f / sc : 0.f;
+        }
+        wave_lds_sync();
+    }
+}
+
+template <int M, bool F32>
+__device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d, const BatchMeta& mt,
+                                   unsigned long long c, FloatSharedLds<M, F32>& L, const unsigned long long* bt,
+                                   int lane, bool restage, Partial& out) {
+    constexpr int S64 = SharedLayout<M>::s64;
+    if (restage) stage_float_shared<M, F32>(J, d, L, lane);
+    const int n = d.n;
+    const unsigned long long R0 = c * mt.chunk;
+    const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
+    // the chunk as a rank window of the single-matrix round
+    FloatJob FJ{};
+    FJ.n = n;
+    FJ.q_begin = R0;
+    FJ.count = R1 - R0;
+    FJ.total = mt.total;
+    FJ.tau = J.tau;
+    FJ.colex = 0;
+    FJ.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
+    FJ.cap = kBatchSharedCap;
+    FJ.defer_cap = kBatchDefer;
+    FJ.fb_entries = reinterpret_cast<unsigned*>(L.queue);   // the wave's queue (segment 0)
+    RoundLds W;
+    W.hdr = reinterpret_cast<PairHdr*>(L.rec);
+    W.incl = reinterpret_cast<unsigned*>(L.rec + kHdrBytes);
+    W.cincl = W.incl + kPrefixBlock;
+    W.ratios = reinterpret_cast<float*>(L.rec + kHdrBytes + kScanBytes);
+    W.wcols = reinterpret_cast<uint4*>(L.rec + kHdrBytes + kScanBytes + kPrefixBlock * 4);
+    W.tv = reinterpret_cast<unsigned char*>(L.tv);
+    // the prefixes holding the window's first and last ranks
+    unsigned long long next = prefix_of_rank<M>(R0, n, bt, kBatchBS);
+    const unsigned long long pi1 = prefix_of_rank<M>(R1 - 1, n, bt, kBatchBS) + 1;
+    double hi = 0.0, lo = 0.0, ab = 0.0;
+    unsigned long long nfb = 0;
+    int gcount = 0;
+    unsigned minors;
+    if constexpr (F32) {
+        if (!mt.all_double) {
+            while (next < pi1) {
+                const double shi = hi, slo = lo, sab = ab;
+                const unsigned long long snfb = nfb;
+                const int sg = gcount;
+                const int ntake = shared_round<M, true, kBatchBS>(FJ, bt, L.cf, next, pi1, W, lane, 0ull, hi, lo, ab,
+                                                                  nfb, gcount, minors);
+                if (gcount > FJ.defer_cap) {
+                    // the round's flagged minors do not fit the queue: the round
+                    // again, in double (every one of its minors counted as refactored)
+                    hi = shi;
+                    lo = slo;
+                    ab = sab;
+                    nfb = snfb;
+                    gcount = sg;
+                    wave_lds_sync();
+                    (void)shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, W, lane, 0ull, hi, lo, ab, nfb,
+                                                           gcount, minors);
+                    if (lane == 0) nfb += minors;
+                }
+                next += (unsigned long long)ntake;
+                wave_lds_sync();
+                relieve_segment<M, S64>(FJ, L.cd, 0ull, gcount, lane, hi, lo, ab);
+            }
+            if (gcount > 0) {
+                __threadfence_block();   // the entries other lanes of the wave stored
+                refactor_queue_groups<M, S64>(L.cd, L.queue, gcount, lane, hi, lo, ab);
+            }
+            wave_reduce_partial(hi, lo, ab, nfb);
+            out = Partial{hi, lo, ab, nfb};
+            return;
+        }
+    }
+    // double rounds (FP64, or FP32-bulk under kF32MinMinors minors: every minor
+    // counted as done in double)
+    while (next < pi1) {
+        const int ntake = shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, W, lane, 0ull, hi, lo, ab, nfb,
+                                                           gcount, minors);
+        if (F32 && lane == 0) nfb += minors;
+        next += (unsigned long long)ntake;
+        wave_lds_sync();
+    }
+    wave_reduce_partial(hi, lo, ab, nfb);
+    out = Partial{hi, lo, ab, nfb};
+}
+
 template <bool F32, int M>
 __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J) {
-    __shared__ FloatWaveLds<M, F32> lds[kBatchWaves];
+    constexpr bool SHARED = M >= 3;
+    using Lds = typename std::conditional<SHARED, FloatSharedLds<M, F32>, FloatWaveLds<M, F32>>::type;
+    __shared__ Lds lds[kBatchWaves];
+    // binomial table C(x, y), x < kBatchMaxN, y <= RADIC_MAX_M, for the prefix rounds
+    __shared__ unsigned long long bt[SHARED ? kBatchMaxN * kBatchBS : 1];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    FloatWaveLds<M, F32>& L = lds[wave];
     constexpr int cls = M - 1;   // class_of(0, M)
     const unsigned long long total = J.header->chunks[cls];
-    // a wave numbered past the class's chunk count would find the queue drained:
-    // it leaves without contending for it
+    // waves numbered past the class's chunk count would find the queue drained:
+    // a workgroup of only such waves leaves at once, the others after the barrier
+    if ((unsigned long long)blockIdx.x * kBatchWaves >= total) return;
+    if constexpr (SHARED) {
+        for (int e = threadIdx.x; e < kBatchMaxN * kBatchBS; e += blockDim.x) {
+            const int x = e / kBatchBS, y = e - x * kBatchBS;
+            bt[e] = g_binom[x * kBinomCols + y];
+        }
+        __syncthreads();
+    }
     if ((unsigned long long)blockIdx.x * kBatchWaves + wave >= total) return;
+    Lds& L = lds[wave];
     const unsigned long long* prefix = J.prefix + (size_t)cls * (J.batch + 1);
     int staged = -1;
     for (;;) {
@@ -388,7 +542,8 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
         const bool restage = b != staged;
         staged = b;
         Partial p{};
-        float_chunk<M, F32>(J, d, mt, c, L, lane, restage, p);
+        if constexpr (SHARED) float_chunk_shared<M, F32>(J, d, mt, c, L, bt, lane, restage, p);
+        else float_chunk<M, F32>(J, d, mt, c, L, lane, restage, p);
         if (lane == 0) J.partials[(size_t)b * kBatchChunksPerMatrix + c] = p;
     }
 }

@@ -227,20 +227,26 @@ __device__ __forceinline__ double refactor_entry_f64(const double* cd, const uns
     return neg ? -d : d;
 }
 
-// Signed term of one queued minor refactored in double by a group of eight
-// lanes (8-aligned in the wave; all eight call together): lane r holds row r of
-// the minor (rows in natural order, from the row-scaled double copy cd), so no
-// register is indexed by a run-time row.  Partial pivoting without exchanges:
-// step k takes the unused row with the largest key |a_rk| (the key of lu_steps,
-// ties to the lower row; the group maximum by three DPP lane moves), broadcasts
-// that row to the group and eliminates the other unused rows with the multipliers
-// and fused multiply-adds of lu_steps.  The permutation's parity is the number
-// of unused rows above each pivot row, summed.  Every lane returns the term.
+// Lanes per minor of the group refactorisation: one row per lane, in groups of
+// eight up to m = 8 and of sixteen beyond.
+template <int M> constexpr int refactor_group() { return M <= 8 ? 8 : 16; }
+
+// Signed term of one queued minor refactored in double by a group of G =
+// refactor_group<M>() lanes (G-aligned in the wave; all G call together): lane r
+// holds row r of the minor (rows in natural order, from the row-scaled double
+// copy cd), so no register is indexed by a run-time row.  Partial pivoting
+// without exchanges: step k takes the unused row with the largest key |a_rk|
+// (the key of lu_steps, ties to the lower row; the group maximum by DPP lane
+// moves: pairs, quads, half rows of 8, rows of 16), broadcasts that row to the
+// group and eliminates the other unused rows with the multipliers and fused
+// multiply-adds of lu_steps.  The permutation's parity is the number of unused
+// rows above each pivot row, summed.  Every lane returns the term.
 template <int M, int ST64 = Layout<M>::st64>
 __device__ __forceinline__ double group_refactor_cols_f64(const double* cd, const int (&c)[M], int lane,
                                                           double& absdet) {
-    static_assert(M <= 8, "one row per lane of a group of eight");
-    const int r = lane & 7, base = lane & ~7;
+    constexpr int G = refactor_group<M>();
+    static_assert(M <= G && G <= 16, "one row per lane of a group");
+    const int r = lane & (G - 1), base = lane & ~(G - 1);
     double a[M];
 #pragma unroll
     for (int j = 0; j < M; ++j) a[j] = r < M ? cd[c[j] * ST64 + r] : 0.0;
@@ -249,12 +255,14 @@ __device__ __forceinline__ double group_refactor_cols_f64(const double* cd, cons
     double det = 1.0;
 #pragma unroll
     for (int k = 0; k < M; ++k) {
-        unsigned key = used ? 0u : pivot_key(a[k], r);   // an unused row's key is >= 8
+        unsigned key = used ? 0u : pivot_key(a[k], r);   // an unused row's key is >= 16 - M > 0
         key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xF, 0xF, false));
         key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xF, 0xF, false));
         key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x141, 0xF, 0xF, false));
+        if constexpr (G == 16)
+            key = max(key, (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x140, 0xF, 0xF, false));
         const int p = pivot_row(key);
-        const unsigned gm = (unsigned)(__ballot(!used) >> base) & 0xFFu;
+        const unsigned gm = (unsigned)(__ballot(!used) >> base) & ((1u << G) - 1u);
         odd ^= (__popc(gm & ((1u << p) - 1u)) & 1) != 0;
         const double piv = __shfl(a[k], base + p, kWave);
         if (k < M - 1) zero |= (piv == 0.0);

@@ -101,18 +101,20 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
 }
 
 
-// Every rank of [lo, hi) factored in double by the wave's eight groups of eight
-// lanes (group_refactor_cols_f64: one row per lane, no per-lane matrix): group g
-// takes the g-th of 8 contiguous sub-ranges, unranks its first sequence
-// (Section 4) and walks the rest with the successor (Section 5); its first lane
-// adds the terms.  bt[x*BS + y] = C(x, y).  Counts the ranks in nvalid.
+// Every rank of [lo, hi) factored in double by the wave's groups of G =
+// refactor_group<M>() lanes (group_refactor_cols_f64: one row per lane, no
+// per-lane matrix): group g takes the g-th of 64/G contiguous sub-ranges,
+// unranks its first sequence (Section 4) and walks the rest with the successor
+// (Section 5); its first lane adds the terms.  bt[x*BS + y] = C(x, y).  Counts
+// the ranks in nvalid.
 template <int M, int BS, int S64>
 __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
                                      unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
                                      double& ab, unsigned long long& nvalid) {
+    constexpr int G = refactor_group<M>(), NG = kWave / G;
     if (hi <= lo) return;
-    const int g = lane >> 3;
-    const unsigned long long per = (hi - lo + 7) / 8;
+    const int g = lane / G;
+    const unsigned long long per = (hi - lo + NG - 1) / NG;
     const unsigned long long s0 = lo + (unsigned long long)g * per;
     const unsigned long long s1 = s0 + per < hi ? s0 + per : hi;
     int col[M];
@@ -120,7 +122,7 @@ __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long
     for (unsigned long long s = 0; s < per; ++s) {
         double ad;
         const double term = group_refactor_cols_f64<M, S64>(cd, col, lane, ad);
-        if (s0 + s < s1 && (lane & 7) == 0) {
+        if (s0 + s < s1 && (lane & (G - 1)) == 0) {
             double sum, err;
             two_sum(h, term, sum, err);
             h = sum;
@@ -132,25 +134,21 @@ __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long
     }
 }
 
-// FP32-bulk, m <= 8, between two rounds of a prefix-shared wave: when the wave's
-// segment of J.fb_entries is more than half full (gcount entries, wave-uniform),
-// the wave refactors them in double here, in whole passes of its eight groups of
-// eight lanes (group g takes entries g, g + 8, ...; its first lane adds the
-// term), and moves the at most seven left to the front of the segment; gcount
-// becomes their number.  This keeps a wave that meets many flagged minors from
-// overflowing its segment (and redoing its blocks in double).  Every lane calls
-// this.
+// Entries [0, count) of a wave's queue q of packed minors (count wave-uniform),
+// refactored in double by the wave's groups of G = refactor_group<M>() lanes:
+// group g takes entries g, g + 64/G, ...; a group past the last entry works on
+// entry 0 and adds nothing; the group's first lane adds the term.  Every lane
+// calls this.
 template <int M, int S64>
-__device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned long long gwave, int& gcount, int lane,
-                                double& hi, double& lo, double& ab) {
-    if (2 * gcount <= J.defer_cap) return;
-    const int F = gcount & ~7;
-    uint4* seg = reinterpret_cast<uint4*>(J.fb_entries) + (size_t)gwave * J.defer_cap;
-    __threadfence_block();   // the entries other lanes of the wave stored
-    for (int e = lane >> 3; e < F; e += 8) {
+__device__ void refactor_queue_groups(const double* cd, const uint4* q, int count, int lane, double& hi, double& lo,
+                                      double& ab) {
+    constexpr int G = refactor_group<M>(), NG = kWave / G;
+    for (int e0 = 0; e0 < count; e0 += NG) {
+        const int e = e0 + lane / G;
+        const bool ok = e < count;
         double ad;
-        const double term = group_refactor_f64<M, S64>(cd, reinterpret_cast<const unsigned*>(seg + e), lane, ad);
-        if ((lane & 7) == 0) {
+        const double term = group_refactor_f64<M, S64>(cd, reinterpret_cast<const unsigned*>(q + (ok ? e : 0)), lane, ad);
+        if (ok && (lane & (G - 1)) == 0) {
             double sum, err;
             two_sum(hi, term, sum, err);
             hi = sum;
@@ -158,7 +156,24 @@ __device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned lo
             ab += ad;
         }
     }
-    // entries [F, gcount) to [0, gcount - F): disjoint, since gcount - F < 8 <= F
+}
+
+// FP32-bulk, between two rounds of a prefix-shared wave: when the wave's segment
+// of J.fb_entries is more than half full (gcount entries, wave-uniform), the
+// wave refactors them in double here, in whole passes of its lane groups
+// (refactor_queue_groups), and moves the fewer than 64/G left to the front of
+// the segment; gcount becomes their number.  This keeps a wave that meets many
+// flagged minors from overflowing its segment.  Every lane calls this.
+template <int M, int S64>
+__device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned long long gwave, int& gcount, int lane,
+                                double& hi, double& lo, double& ab) {
+    constexpr int NG = kWave / refactor_group<M>();   // groups per wave
+    if (2 * gcount <= J.defer_cap) return;
+    const int F = gcount - gcount % NG;
+    uint4* seg = reinterpret_cast<uint4*>(J.fb_entries) + (size_t)gwave * J.defer_cap;
+    __threadfence_block();   // the entries other lanes of the wave stored
+    refactor_queue_groups<M, S64>(cd, seg, F, lane, hi, lo, ab);
+    // entries [F, gcount) to [0, gcount - F): disjoint, since gcount - F < NG <= F
     const int rest = gcount - F;
     uint4 v = make_uint4(0u, 0u, 0u, 0u);
     if (lane < rest) v = seg[F + lane];
@@ -170,11 +185,10 @@ __device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned lo
 // minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
 // segment overflowed drops its float sums and redoes its own blocks (BLOCK
 // prefixes of m-KT columns: gwave, gwave + nwaves, ...; colex blocks prefix by
-// prefix) in double, eight lanes per minor.  The entries
-// of the other waves are pooled and refactored in double by groups of eight
-// threads of the workgroup, in a fixed order (group g takes entries g, g + G, ...;
-// its first lane adds the term).  segn: a workgroup LDS
-// array of 16.  Every thread of the workgroup calls this.  Reads the binomial
+// prefix) in double, a group of refactor_group<M>() lanes per minor.  The
+// entries of the other waves are pooled and refactored in double by such groups
+// of the workgroup's threads, in a fixed order (group g takes entries g, g + NG,
+// ...; its first lane adds the term).  segn: a workgroup LDS array of 16.  Every thread of the workgroup calls this.  Reads the binomial
 // slice bt (stride BS) and the row-scaled double copy cd (column stride S64).
 template <int M, int KT, int BLOCK, int BS, int S64>
 __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt, const double* cd, int gcount,
@@ -206,9 +220,11 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
     for (int w = 0; w < waves; ++w)
         if (segn[w] <= (unsigned)J.defer_cap) E += segn[w];
     const unsigned long long w0 = (unsigned long long)blockIdx.x * waves;
-    // eight lanes per entry: group g of the workgroup takes entries g, g + G, ...
-    const unsigned g = threadIdx.x >> 3, G = blockDim.x >> 3;
-    for (unsigned e = g; e < E; e += G) {
+    // a group of GL lanes per entry: group g of the workgroup takes entries g,
+    // g + NG, ...
+    constexpr unsigned GL = refactor_group<M>();
+    const unsigned g = threadIdx.x / GL, NG = blockDim.x / GL;
+    for (unsigned e = g; e < E; e += NG) {
         // the segment holding entry e (overflowed segments skipped)
         int w = 0;
         unsigned pos = e;
@@ -220,7 +236,7 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
         const unsigned* ent = J.fb_entries + ((size_t)(w0 + w) * J.defer_cap + pos) * 4;
         double ad;
         const double term = group_refactor_f64<M, S64>(cd, ent, lane, ad);
-        if ((lane & 7) == 0) {
+        if ((lane & (GL - 1)) == 0) {
             double sum, err;
             two_sum(hi, term, sum, err);
             hi = sum;

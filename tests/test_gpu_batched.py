@@ -57,6 +57,30 @@ def test_mixed_batch(precision):
     check(mats, res, precision)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_bulk"])
+@pytest.mark.parametrize("tau", [1.0 / 1024, math.inf])
+def test_float_prefix_rounds(precision, tau):
+    # float matrices above 4096 minors for m = 3..10 (their chunks run the
+    # prefix-shared round; two wide ones, several chunks each), one with nearly
+    # dependent rows (many FP32-bulk minors flagged); tau = inf flags every
+    # FP32-bulk minor, which exercises the wave's queue refactorisation and the
+    # rounds done again in double
+    rng = np.random.default_rng(11)
+    shapes = [(3, 40), (4, 60), (5, 24), (6, 20), (7, 18), (8, 18), (9, 17), (10, 18), (8, 16)]
+    mats = [rng.standard_normal(s) for s in shapes]
+    mats.append(workloads.near_dependent_rows(7, 16, seed=12, eps=1e-6))
+    mats.append(rng.integers(-9, 10, size=(7, 15)).astype(np.int32))
+    radic.set_fallback_tau(tau)
+    print(f"[case] batched prefix rounds {precision} tau={tau}", flush=True)
+    res = radic.radic_det_batched(radic.Batch(mats), precision)
+    check(mats, res, precision)
+    for A, r in zip(mats, res):
+        if A.dtype == np.float64 and precision == "fp32_bulk" and tau == math.inf:
+            assert r["n_fallback"] == math.comb(A.shape[1], A.shape[0])
+        if precision == "fp64":
+            assert r["n_fallback"] == 0
+
+
 def test_every_row_count():
     # one float and one int matrix for every m = 1..12 (each has its own class kernel)
     rng = np.random.default_rng(2)
