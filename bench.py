@@ -34,9 +34,11 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # summary and commands are in profiles/k_radic_shared_8x32.md).  They hold for
 # the kernel sources they were taken on: `traffic` is reported only while the
 # sources hash to the same value.
-KERNEL_SOURCES = ["kernels_shared.hip", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h", "radic_internal.h",
-                  "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "1226dd564bd723c5bd1272d29263b48351485b3b00fcf4852925a85167193319", "fp64": 671184, "fp32_bulk": 3524917}
+KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h",
+                  "radic_internal.h", "radic_api.cpp"]
+PROFILED_TRAFFIC = {"sources_sha256": "838fa61f2ffee2a0bf8a5c057e7887e6954bc420a4732b268fb45ed0f703a290", "fp64": 406368, "fp32_bulk": 3052832}
+# FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
+PROFILED_FLOPS = {"fp64": {"fp32": 2450688, "fp64": 460292608}, "fp32_bulk": {"fp32": 350846464, "fp64": 203616576}}
 
 
 def kernel_sources_sha256():
@@ -311,6 +313,21 @@ def traffic_for(form, enumeration):
     return PROFILED_TRAFFIC[form]
 
 
+def rocprof_flops(form, enumeration, kernel_ms):
+    """FLOPs per launch of the prefix-shared kernel from its rocprofv3 counters
+    (SQ_INSTS_VALU_FLOPS_FP32/FP64 x 64), over this run's kernel time; None
+    once the kernel sources differ from those profiled."""
+    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+        return None
+    f = PROFILED_FLOPS[form]
+    peak = PEAK_FP32_TFLOPS if form == "fp32_bulk" else PEAK_FP64_TFLOPS
+    t32 = f["fp32"] / (kernel_ms * 1e-3) / 1e12
+    t64 = f["fp64"] / (kernel_ms * 1e-3) / 1e12
+    return {"fp32_flop": f["fp32"], "fp64_flop": f["fp64"], "fp32_tflops": t32, "fp64_tflops": t64,
+            "frac_of_form_peak": (t32 if form == "fp32_bulk" else t64) / peak,
+            "source": "rocprofv3 counters per launch (profiles/k_radic_shared_8x32.md)"}
+
+
 def kernel_name(enumeration, form):
     if enumeration == "per_minor":
         return "k_radic_float<8,true,false,true>" if form == "fp32_bulk" else "k_radic_float<8,false,false,false>"
@@ -508,6 +525,7 @@ def main():
                                             "per_unit": f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} "
                                                         f"FLOP per minor x {total} minors = {flop:.4g} FLOP, "
                                                         f"a different method's work"},
+                     "rocprof_flops": rocprof_flops(dom, args.enumeration, dom_ms),
                      "kernel_ms": dom_ms, "launches_timed": len(timed),
                      "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},
         "cpu_baseline": cpu,
