@@ -243,7 +243,11 @@ def other_workloads(radic, binding, workloads, torch, dev, args):
     gold = read_golden("workload5_batch4096.txt")
     batch = radic.Batch(mats, device=dev)
     res = {}
+    tuned = {}
     for p in ("fp32_bulk", "fp64"):
+        # the persistent kernels' chunk size from the library's autotuner, timed
+        # on this batch; the graph is captured with the tuned shape
+        tuned[p] = radic.autotune_batched(batch, precision=p)[0]
         gph = radic.BatchGraph(batch, precision=p)
         for _ in range(3):
             gph.launch()
@@ -275,8 +279,10 @@ def other_workloads(radic, binding, workloads, torch, dev, args):
         res[p] = {"ms_per_launch": ms, "subdet_per_s": minors / (ms * 1e-3), "mismatches_vs_oracle": int(bad),
                   "checked": len(batch_list)}
     out["w5_batch4096"] = {"minors": 342865835, "float_forms": res,
+                           "tuned_subsets_per_lane": tuned,
                            "note": "one HIP-graph replay per launch; int32 matrices exact (bit-exact check), "
-                                   "float64 matrices in the named precision"}
+                                   "float64 matrices in the named precision; chunk sizes (64 x subsets per "
+                                   "lane ranks) chosen by radic_autotune_batched on this batch beforehand"}
     return out
 
 

@@ -292,11 +292,31 @@ int radic_graph_destroy(void *hGraph);
  * candidate (subsets per lane, workgroup size) pairs for the given shape and
  * precision on the current device with HIP events, on a synthetic matrix of
  * that shape, and records the fastest for later calls.  Synchronous.
- * kind: RADIC_WS_DET (prec applies), RADIC_WS_INT or RADIC_WS_BATCHED (m is the
- * row count class, n ignored).  hBest (may be null) receives {subsets_per_lane,
- * block_size}.  radic_tune_save/load persist the table as text.
+ * kind: RADIC_WS_DET (prec applies), RADIC_WS_INT or RADIC_WS_BATCHED (m and n
+ * ignored; prec 0 or 1 tunes the float classes on a synthetic float batch, prec 2
+ * the exact classes on a synthetic int32 batch).  A shape tuned for n serves
+ * every n of its bucket (each n up to 16, runs of 8 up to 64, then of 32).
+ * hBest (may be null) receives {subsets_per_lane, block_size}.
+ * radic_tune_save/load persist the table as text; the table names the device
+ * architecture and the library version (radic_version), and radic_tune_load
+ * refuses (RADIC_EINVAL) a table of another version or, when a device is
+ * current, of another architecture.
  */
 int radic_autotune(int kind, int m, int n, int prec, int *hBest, hipStream_t stream);
+/*
+ * radic_autotune_batched -- launch-shape tuning of radic_det_batched on the
+ * caller's own batch (Section 5's granularity for that workload): times each
+ * candidate subsets-per-lane value (the chunks of both the float and the exact
+ * classes hold at least 64 x that many ranks) with radic_det_batched on the given
+ * arguments, and records the fastest for later batched calls of any batch in
+ * this process (both the `prec` float classes and the exact classes).  Same
+ * arguments as radic_det_batched (dOut and dWork are overwritten), plus hBest
+ * (may be null) receiving {subsets_per_lane, block_size}.  Synchronous.
+ * Errors: as radic_det_batched; EDEVICE if no candidate ran.
+ */
+int radic_autotune_batched(const radic_matrix_desc *dDesc, int batch, const double *dF64,
+                           const int32_t *dI32, int prec, radic_batch_result *dOut, void *dWork,
+                           size_t work_bytes, int *hBest, hipStream_t stream);
 int radic_tune_save(const char *path);
 int radic_tune_load(const char *path);
 /* Force a launch shape (0 = tuned/default) for subsequent calls; for tests and sweeps. */

@@ -6,7 +6,7 @@ m x m minor.  The work runs in hand-written HIP kernels behind the C ABI of
 ``include/radic.h``; this package is a thin ctypes binding with the same names.
 """
 from .binding import (  # noqa: F401
-    Batch, BatchGraph, autotune, radic_det_batched, tune_load, tune_save,
+    Batch, BatchGraph, autotune, autotune_batched, radic_det_batched, tune_load, tune_save,
     PRECISIONS, RADIC_EDEVICE, RADIC_EINVAL, RADIC_ENONFINITE, RADIC_ENOTSUP, RADIC_EOVERFLOW, RADIC_EWORKSPACE,
     RADIC_FP32_BULK, RADIC_FP64, RADIC_MAX_M, RADIC_MAX_N, RADIC_OK, RADIC_WS_BATCHED, RADIC_WS_DET, RADIC_WS_INT,
     RadicError, host_binomial, host_prime, host_unrank, lib, profile_enable, profile_read, profile_read_launches, radic_det,

@@ -75,6 +75,7 @@ SIGNATURES = {
     "radic_graph_launch": (_i, [_vp, _vp]),
     "radic_graph_destroy": (_i, [_vp]),
     "radic_autotune": (_i, [_i, _i, _i, _i, _ip, _vp]),
+    "radic_autotune_batched": (_i, [_vp, _i, _vp, _vp, _i, _vp, _vp, _sz, _ip, _vp]),
     "radic_tune_save": (_i, [ctypes.c_char_p]),
     "radic_tune_load": (_i, [ctypes.c_char_p]),
     "radic_set_launch": (_i, [_i, _i]),
@@ -280,6 +281,16 @@ def autotune(kind, m=0, n=0, precision="fp64", stream=None):
     prec = {"fp64": 0, "fp32_bulk": 1, "exact": 2}[precision] if isinstance(precision, str) else int(precision)
     best = (ctypes.c_int * 2)()
     _check(lib().radic_autotune(int(kind), int(m), int(n), prec, best, _stream_handle(stream)), "radic_autotune")
+    return best[0], best[1]
+
+
+def autotune_batched(batch, precision="fp64", stream=None):
+    """Time the batched chunk sizes on this Batch itself and keep the fastest for
+    later batched calls; returns (subsets_per_lane, block)."""
+    best = (ctypes.c_int * 2)()
+    desc, nb, f64, i32, prec, out, work, nwork = batch.args(precision)
+    _check(lib().radic_autotune_batched(desc, nb, f64, i32, prec, out, work, nwork, best, _stream_handle(stream)),
+           "radic_autotune_batched")
     return best[0], best[1]
 
 

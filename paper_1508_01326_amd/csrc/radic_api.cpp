@@ -13,6 +13,7 @@
 #include <mutex>
 #include <new>
 #include <tuple>
+#include <string>
 #include <vector>
 
 #include "radic_internal.h"
@@ -220,7 +221,11 @@ struct Shape {
 // per block); their default spl.
 constexpr int kSharedSplFloat = 64;
 constexpr int kSharedSplInt = 48;
-static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;   // (kind, prec, m, n) -> shape
+// Tuned launch shapes, (kind, prec, m, column bucket) -> shape.  A shape is
+// tuned on one n and serves the n of its bucket: every n up to 16, then runs of
+// 8 up to 64, then of 32.
+static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;
+static int n_bucket(int n) { return n <= 16 ? n : (n <= 64 ? (n + 7) / 8 * 8 : (n + 31) / 32 * 32); }
 static int g_force_spl = 0, g_force_block = 0;
 static int g_enumeration = RADIC_ENUM_AUTO;
 static double g_tau = 1.0 / 1024.0;
@@ -242,7 +247,7 @@ static Shape pick_shape(int kind, int prec, int m, int n) {
     Shape s = default_shape(kind, prec, m, n);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_tuned.find(std::make_tuple(kind, prec, m, n));
+        auto it = g_tuned.find(std::make_tuple(kind, prec, m, n_bucket(n)));
         if (it != g_tuned.end()) {
             s = it->second;
             s.spl_set = true;
@@ -1032,7 +1037,7 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
         for (int b = 0; b < batch; ++b) {
             const int mm = 2 + (int)(rng.next() % 9);
             const int nn = mm + (int)(rng.next() % (25 - mm));
-            const int dt = prec == 2 ? 1 : (b % 2);
+            const int dt = prec == 2 ? 1 : 0;   // the exact or the float classes alone
             desc[(size_t)b] = radic_matrix_desc{mm, nn, dt, 0, dt ? io : fo, nn};
             for (int e = 0; e < mm * nn; ++e) {
                 if (dt) hi.push_back((int)(rng.next() % 256));
@@ -1079,7 +1084,7 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
     g_force_block = saved_block;
     if (best.spl == 0) return RADIC_EDEVICE;
     const int key_prec = kind == RADIC_WS_DET ? prec : (kind == RADIC_WS_INT ? 0 : prec);
-    const int km = kind == RADIC_WS_BATCHED ? 0 : m, kn = kind == RADIC_WS_BATCHED ? 0 : n;
+    const int km = kind == RADIC_WS_BATCHED ? 0 : m, kn = kind == RADIC_WS_BATCHED ? 0 : n_bucket(n);
     g_tuned[std::make_tuple(kind, key_prec, km, kn)] = best;
     if (hBest) {
         hBest[0] = best.spl;
@@ -1088,12 +1093,79 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
     return RADIC_OK;
 }
 
+// The current device's architecture name without feature suffixes ("gfx950"),
+// or "none" without a usable device.
+static std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t pr;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "none";
+    }
+    std::string a = pr.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+constexpr int kBatchBlock = 256;   // the batched persistent kernels' workgroup size
+
+int radic_autotune_batched(const radic_matrix_desc* dDesc, int batch, const double* dF64, const int32_t* dI32,
+                           int prec, radic_batch_result* dOut, void* dWork, size_t work_bytes, int* hBest,
+                           hipStream_t stream) {
+    if (!dDesc || !dOut || batch <= 0) return RADIC_EINVAL;
+    if (prec != RADIC_FP64 && prec != RADIC_FP32_BULK) return RADIC_EINVAL;
+    if (batch > (1 << 24)) return RADIC_ENOTSUP;
+    int rc = check_workspace(dWork, work_bytes, batched_workspace_bytes(batch));
+    if (rc != RADIC_OK) return rc;
+    if ((rc = ensure_device()) != RADIC_OK) return rc;
+    int saved_spl, saved_block;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        saved_spl = g_force_spl;
+        saved_block = g_force_block;
+    }
+    // one subsets-per-lane value for the float and the exact classes: the chunk
+    // sizes of both grow with it, and the classes of one launch run in sequence
+    const int spls[] = {8, 16, 32, 64, 128};
+    float best_ms = 0.f;
+    int best = 0;
+    for (int spl : spls) {
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            g_force_spl = spl;
+            g_force_block = 0;
+        }
+        int trc = RADIC_OK;
+        const float ms = time_runs([&]() { return batched_launch(dDesc, batch, dF64, dI32, prec, dOut, dWork, stream,
+                                                                 false); },
+                                   stream, 3, &trc);
+        if (trc != RADIC_OK) continue;
+        if (best == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = spl;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_force_spl = saved_spl;
+    g_force_block = saved_block;
+    if (best == 0) return RADIC_EDEVICE;
+    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, prec, 0, 0)] = Shape{best, kBatchBlock};
+    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, 2, 0, 0)] = Shape{best, kBatchBlock};
+    if (hBest) {
+        hBest[0] = best;
+        hBest[1] = kBatchBlock;
+    }
+    return RADIC_OK;
+}
+
 int radic_tune_save(const char* path) {
     if (!path) return RADIC_EINVAL;
+    const std::string arch = device_arch();
     FILE* f = std::fopen(path, "w");
     if (!f) return RADIC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "# radic launch-shape table v1: kind prec m n subsets_per_lane block\n");
+    std::fprintf(f, "# radic launch-shape table: kind prec m n_bucket subsets_per_lane block\n");
+    std::fprintf(f, "arch %s version %d\n", arch.c_str(), radic_version());
     for (const auto& kv : g_tuned)
         std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
                      std::get<3>(kv.first), kv.second.spl, kv.second.block);
@@ -1107,8 +1179,22 @@ int radic_tune_load(const char* path) {
     std::map<std::tuple<int, int, int, int>, Shape> t;
     char line[256];
     int rc = RADIC_OK;
+    bool header = false;
+    const std::string arch = device_arch();
     while (std::fgets(line, sizeof(line), f)) {
         if (line[0] == '#' || line[0] == '\n') continue;
+        if (!header) {
+            // the table's device and library: shapes tuned elsewhere are refused
+            char a[64];
+            int v = 0;
+            if (std::sscanf(line, "arch %63s version %d", a, &v) != 2 || v != radic_version() ||
+                (arch != "none" && arch != a)) {
+                rc = RADIC_EINVAL;
+                break;
+            }
+            header = true;
+            continue;
+        }
         int k, p, m, n, spl, block;
         if (std::sscanf(line, "%d %d %d %d %d %d", &k, &p, &m, &n, &spl, &block) != 6 || spl < 1 || spl > 4096 ||
             block < kWave || block > kMaxBlock || block % kWave) {
@@ -1118,6 +1204,7 @@ int radic_tune_load(const char* path) {
         t[std::make_tuple(k, p, m, n)] = Shape{spl, block};
     }
     std::fclose(f);
+    if (rc == RADIC_OK && !header) rc = RADIC_EINVAL;
     if (rc != RADIC_OK) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     for (const auto& kv : t) g_tuned[kv.first] = kv.second;

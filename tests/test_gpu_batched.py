@@ -164,3 +164,20 @@ def test_autotune_batched_and_int():
     mats = mixed_batch(30, seed=8)
     res = radic.radic_det_batched(radic.Batch(mats), "fp32_bulk")
     check(mats, res, "fp32_bulk")
+
+
+def test_autotune_on_own_batch():
+    # tuning on the caller's batch records one chunk size for both kinds of
+    # classes; later calls and graphs captured after it use it and stay correct
+    rng = np.random.default_rng(13)
+    mats = [rng.standard_normal((8, 18)), rng.integers(-9, 10, size=(9, 17)).astype(np.int32),
+            rng.standard_normal((5, 24))] + mixed_batch(20, seed=14)
+    B = radic.Batch(mats)
+    print("[case] autotune on own batch", flush=True)
+    spl, block = radic.autotune_batched(B, "fp32_bulk")
+    assert spl in (8, 16, 32, 64, 128) and block == 256
+    check(mats, B.results(), "fp32_bulk")        # the last tuning run's results
+    res = radic.radic_det_batched(B, "fp32_bulk")
+    check(mats, res, "fp32_bulk")
+    chunk, _ = radic.host_batch_chunking(0, 8, 18, spl)
+    assert chunk >= 64 * spl
