@@ -60,6 +60,23 @@ __device__ __forceinline__ double mulmod(double a, double b, double p, double pi
     return mod_fix(r, p);
 }
 
+// a*b up to a multiple of p, without the range fix: for integers |a|, |b| <=
+// 4.1 p (p < 2^31) the quotient estimate q is off by at most one, h - q p and
+// then h - q p + l are exact, so r = a b - q p with |r| < 2.01 p.  Sums and
+// differences of two such results may be fed back in.
+__device__ __forceinline__ double mulmod_lazy(double a, double b, double p, double pinv) {
+    const double h = a * b;
+    const double l = __builtin_fma(a, b, -h);
+    const double q = __builtin_floor(h * pinv);
+    return __builtin_fma(-q, p, h) + l;
+}
+
+// An integer |x| < 2^52 reduced to [-p, 2p) (same residue), and to [0, p).
+__device__ __forceinline__ double reduce_lazy(double x, double p, double pinv) {
+    return __builtin_fma(-__builtin_floor(x * pinv), p, x);
+}
+__device__ __forceinline__ double canon(double x, double p, double pinv) { return mod_fix(reduce_lazy(x, p, pinv), p); }
+
 __device__ __forceinline__ double addmod(double a, double b, double p) {
     const double r = a + b;
     return r >= p ? r - p : r;

@@ -33,16 +33,19 @@ struct IntSlot {
     int pad;
 };
 
-// sum_j w_j x_j mod p, the products reduced one by one and their sum (below
-// M p < 2^35, exact) once
+// sum_j w_j x_j mod p in [0, p), for |w_j|, |x_j| <= 4.1 p: the lazy products
+// (each below 2.01 p) summed exactly (below 2^36) and reduced once
 template <int M>
 __device__ __forceinline__ double dot_mod(const double (&w)[M], const double (&x)[M], double p, double pinv) {
     double s = 0.0;
 #pragma unroll
-    for (int j = 0; j < M; ++j) s += mulmod(w[j], x[j], p, pinv);
-    const double q = __builtin_floor(s * pinv);
-    return mod_fix(__builtin_fma(-q, p, s), p);
+    for (int j = 0; j < M; ++j) s += mulmod_lazy(w[j], x[j], p, pinv);
+    return canon(s, p, pinv);
 }
+
+// Accumulated lazy terms (each below 6.1 p) are reduced after at most this
+// many steps of a lane, so the running sum stays an exact double (< 2^51).
+constexpr unsigned kAccRun = 1u << 16;
 
 // Step K of the prefix's fraction-free elimination, column by column
 // (left-looking).  Column c_K is read in the lane's current row order `rel` (4
@@ -51,7 +54,10 @@ __device__ __forceinline__ double dot_mod(const double (&w)[M], const double (&x
 // nonzero entry, and an exchange swaps the two rows of L and of the column and
 // is recorded in rel, so that later columns are read already exchanged.  L_iK
 // keeps the column's entries below the pivot (the step's multipliers).  Every
-// residue sees the same operations as in the row-by-row form.
+// residue sees the same operations as in the row-by-row form.  The updates use
+// lazy products (values below 4.1 p in magnitude, same residues); the column is
+// brought to [0, p) before its pivot test, so pivots, multipliers and the zero
+// test are those of canonical residues.
 template <int M, int P, int K>
 __device__ __forceinline__ void int_left_steps(double (&L)[M][P], double (&u)[P], const double* cr, int stride,
                                                const int (&c)[P], double p, double pinv, double& Pk, double& D,
@@ -65,12 +71,16 @@ __device__ __forceinline__ void int_left_steps(double (&L)[M][P], double (&u)[P]
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int i = k + 1; i < M; ++i) {
-                x[i] = submod(mulmod(u[k], x[i], p, pinv), mulmod(L[i][k], x[k], p, pinv), p);
+                x[i] = mulmod_lazy(u[k], x[i], p, pinv) - mulmod_lazy(L[i][k], x[k], p, pinv);
                 // an empty register constraint: keeps the compiler's instruction
                 // combining from folding the whole chain of reductions (whose
                 // compile time otherwise explodes from m = 8); no code
                 asm volatile("" : "+v"(x[i]));
             }
+        }
+        if constexpr (K > 0) {
+#pragma unroll
+            for (int i = K; i < M; ++i) x[i] = canon(x[i], p, pinv);
         }
         unsigned best = 0;
 #pragma unroll
@@ -184,23 +194,24 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
                 pw0[j] = (j == P) ? 1.0 : 0.0;
                 pw1[j] = (j == P + 1) ? 1.0 : 0.0;
             }
+// (lazy residues: each entry below 2.01 p in magnitude)
 #pragma unroll
             for (int k = P - 1; k >= 0; --k) {
                 double d0 = 0.0, d1 = 0.0;
 #pragma unroll
                 for (int i = k + 1; i < M; ++i) {
-                    d0 += mulmod(pw0[i], L[i][k], p, pinv);
-                    d1 += mulmod(pw1[i], L[i][k], p, pinv);
+                    d0 += mulmod_lazy(pw0[i], L[i][k], p, pinv);
+                    d1 += mulmod_lazy(pw1[i], L[i][k], p, pinv);
                 }
-                d0 = mod_fix(__builtin_fma(-__builtin_floor(d0 * pinv), p, d0), p);
-                d1 = mod_fix(__builtin_fma(-__builtin_floor(d1 * pinv), p, d1), p);
+                d0 = reduce_lazy(d0, p, pinv);
+                d1 = reduce_lazy(d1, p, pinv);
 #pragma unroll
                 for (int j = k + 1; j < M; ++j) {
-                    pw0[j] = mulmod(pw0[j], u[k], p, pinv);
-                    pw1[j] = mulmod(pw1[j], u[k], p, pinv);
+                    pw0[j] = mulmod_lazy(pw0[j], u[k], p, pinv);
+                    pw1[j] = mulmod_lazy(pw1[j], u[k], p, pinv);
                 }
-                pw0[k] = submod(pw0[k], d0, p);
-                pw1[k] = submod(pw1[k], d1, p);
+                pw0[k] -= d0;   // was 0: the unit rows sit at m-2, m-1
+                pw1[k] -= d1;
             }
             prel = rel;
             // 1 / D for every prefix of the round: Montgomery's batch inversion
@@ -324,25 +335,31 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
             int ia = 0, ib = 1;
             if (active) unrank_pair(g0 - (s > 0 ? incl[s - 1] : 0u) + h.lo, h.r, ia, ib);
             double2 ta = tv[h.toff + ia];
-            for (unsigned k = 0; k < chunk; ++k) {
-                const bool valid = g0 + k < gend;
-                const double2 tb = tv[h.toff + ib];
-                const double cross = submod(mulmod(ta.x, tb.y, p, pinv), mulmod(ta.y, tb.x, p, pinv), p);
-                double term = mulmod(h.F, cross, p, pinv);
-                if (((ia + ib) & 1) && term != 0.0) term = p - term;
-                if (valid) acc = addmod(acc, term, p);
-                if (++ib >= h.r) {
-                    ++ia;
-                    ib = ia + 1;
-                    if (ib >= h.r) {
-                        s = min(s + 1, ntake - 1);
-                        h = slot[s];
-                        ia = 0;
-                        ib = 1;
+            // lazy terms (below 2.01 p) summed exactly, reduced every kAccRun steps
+            double run = 0.0;
+            for (unsigned k0 = 0; k0 < chunk; k0 += kAccRun) {
+                const unsigned k1 = min(chunk, k0 + kAccRun);
+                for (unsigned k = k0; k < k1; ++k) {
+                    const bool valid = g0 + k < gend;
+                    const double2 tb = tv[h.toff + ib];
+                    const double cross = mulmod_lazy(ta.x, tb.y, p, pinv) - mulmod_lazy(ta.y, tb.x, p, pinv);
+                    const double term = mulmod_lazy(h.F, cross, p, pinv);
+                    if (valid) run += ((ia + ib) & 1) ? -term : term;
+                    if (++ib >= h.r) {
+                        ++ia;
+                        ib = ia + 1;
+                        if (ib >= h.r) {
+                            s = min(s + 1, ntake - 1);
+                            h = slot[s];
+                            ia = 0;
+                            ib = 1;
+                        }
+                        ta = tv[h.toff + ia];
                     }
-                    ta = tv[h.toff + ia];
                 }
+                run = reduce_lazy(run, p, pinv);
             }
+            acc = addmod(acc, canon(run, p, pinv), p);
         }
         rbase += round_total;
         next += (unsigned long long)ntake;

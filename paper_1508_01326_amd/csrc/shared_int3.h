@@ -118,27 +118,28 @@ __device__ void int_group_range(const double* cr, int n, const unsigned long lon
                 pw1[j] = (j == P + 1) ? 1.0 : 0.0;
                 pw2[j] = (j == P + 2) ? 1.0 : 0.0;
             }
+// (lazy residues: each entry below 2.01 p in magnitude)
 #pragma unroll
             for (int k = P - 1; k >= 0; --k) {
                 double d0 = 0.0, d1 = 0.0, d2 = 0.0;
 #pragma unroll
                 for (int i = k + 1; i < M; ++i) {
-                    d0 += mulmod(pw0[i], L[i][k], p, pinv);
-                    d1 += mulmod(pw1[i], L[i][k], p, pinv);
-                    d2 += mulmod(pw2[i], L[i][k], p, pinv);
+                    d0 += mulmod_lazy(pw0[i], L[i][k], p, pinv);
+                    d1 += mulmod_lazy(pw1[i], L[i][k], p, pinv);
+                    d2 += mulmod_lazy(pw2[i], L[i][k], p, pinv);
                 }
-                d0 = mod_fix(__builtin_fma(-__builtin_floor(d0 * pinv), p, d0), p);
-                d1 = mod_fix(__builtin_fma(-__builtin_floor(d1 * pinv), p, d1), p);
-                d2 = mod_fix(__builtin_fma(-__builtin_floor(d2 * pinv), p, d2), p);
+                d0 = reduce_lazy(d0, p, pinv);
+                d1 = reduce_lazy(d1, p, pinv);
+                d2 = reduce_lazy(d2, p, pinv);
 #pragma unroll
                 for (int j = k + 1; j < M; ++j) {
-                    pw0[j] = mulmod(pw0[j], u[k], p, pinv);
-                    pw1[j] = mulmod(pw1[j], u[k], p, pinv);
-                    pw2[j] = mulmod(pw2[j], u[k], p, pinv);
+                    pw0[j] = mulmod_lazy(pw0[j], u[k], p, pinv);
+                    pw1[j] = mulmod_lazy(pw1[j], u[k], p, pinv);
+                    pw2[j] = mulmod_lazy(pw2[j], u[k], p, pinv);
                 }
-                pw0[k] = submod(pw0[k], d0, p);
-                pw1[k] = submod(pw1[k], d1, p);
-                pw2[k] = submod(pw2[k], d2, p);
+                pw0[k] -= d0;   // was 0: the unit rows sit at m-3 .. m-1
+                pw1[k] -= d1;
+                pw2[k] -= d2;
             }
             prel = rel;
             // the minor's denominator: step k scales the m-1-k rows below its
@@ -285,38 +286,44 @@ __device__ void int_group_range(const double* cr, int n, const unsigned long lon
                 ib = t3[1];
                 ic = t3[2];
             }
-            double wx, wy, wz;   // F (u_a x u_b) mod p
+            double wx, wy, wz;   // F (u_a x u_b), lazy residues below 2.01 p
             auto pair = [&]() {
                 const uint4 qa = tv[h.toff + ia], qb = tv[h.toff + ib];
                 const double ax = (double)qa.x, ay = (double)qa.y, az = (double)qa.z;
                 const double bx = (double)qb.x, by = (double)qb.y, bz = (double)qb.z;
-                wx = mulmod(h.F, submod(mulmod(ay, bz, p, pinv), mulmod(az, by, p, pinv), p), p, pinv);
-                wy = mulmod(h.F, submod(mulmod(az, bx, p, pinv), mulmod(ax, bz, p, pinv), p), p, pinv);
-                wz = mulmod(h.F, submod(mulmod(ax, by, p, pinv), mulmod(ay, bx, p, pinv), p), p, pinv);
+                wx = mulmod_lazy(h.F, mulmod_lazy(ay, bz, p, pinv) - mulmod_lazy(az, by, p, pinv), p, pinv);
+                wy = mulmod_lazy(h.F, mulmod_lazy(az, bx, p, pinv) - mulmod_lazy(ax, bz, p, pinv), p, pinv);
+                wz = mulmod_lazy(h.F, mulmod_lazy(ax, by, p, pinv) - mulmod_lazy(ay, bx, p, pinv), p, pinv);
             };
             pair();
-            for (unsigned k = 0; k < chunk; ++k) {
-                const bool valid = g0 + k < gend;
-                const uint4 qc = tv[h.toff + ic];
-                // sum of three reduced products, below 3 p < 2^33: exact
-                const double t = mulmod(wx, (double)qc.x, p, pinv) + mulmod(wy, (double)qc.y, p, pinv) +
-                                 mulmod(wz, (double)qc.z, p, pinv);
-                const double d = mod_fix(__builtin_fma(-__builtin_floor(t * pinv), p, t), p);
-                if (valid) acc = addmod(acc, d, p);
-                // next triple: c, then b, then a, then the next group
-                if (++ic >= h.r) {
-                    if (++ib >= h.r - 1) {
-                        if (++ia >= h.r - 2) {
-                            s = min(s + 1, ntake - 1);
-                            h = slot[s];
-                            ia = 0;
+            // each minor's three lazy products (below 6.1 p together) summed
+            // exactly, reduced every kAccRun steps
+            double run = 0.0;
+            for (unsigned k0 = 0; k0 < chunk; k0 += kAccRun) {
+                const unsigned k1 = min(chunk, k0 + kAccRun);
+                for (unsigned k = k0; k < k1; ++k) {
+                    const bool valid = g0 + k < gend;
+                    const uint4 qc = tv[h.toff + ic];
+                    const double t = mulmod_lazy(wx, (double)qc.x, p, pinv) + mulmod_lazy(wy, (double)qc.y, p, pinv) +
+                                     mulmod_lazy(wz, (double)qc.z, p, pinv);
+                    if (valid) run += t;
+                    // next triple: c, then b, then a, then the next group
+                    if (++ic >= h.r) {
+                        if (++ib >= h.r - 1) {
+                            if (++ia >= h.r - 2) {
+                                s = min(s + 1, ntake - 1);
+                                h = slot[s];
+                                ia = 0;
+                            }
+                            ib = ia + 1;
                         }
-                        ib = ia + 1;
+                        ic = ib + 1;
+                        pair();
                     }
-                    ic = ib + 1;
-                    pair();
                 }
+                run = reduce_lazy(run, p, pinv);
             }
+            acc = addmod(acc, canon(run, p, pinv), p);
         }
         rbase += round_total;
         next += (unsigned long long)ntake;
