@@ -36,7 +36,7 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # sources hash to the same value.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "838fa61f2ffee2a0bf8a5c057e7887e6954bc420a4732b268fb45ed0f703a290", "fp64": 406368, "fp32_bulk": 3052832}
+PROFILED_TRAFFIC = {"sources_sha256": "efa2a19483b16846ed6ceab17ea929f1f0171fb1d3035cceb87ba7253f6cfa0d", "fp64": 406368, "fp32_bulk": 3052832}
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
 PROFILED_FLOPS = {"fp64": {"fp32": 2450688, "fp64": 460292608}, "fp32_bulk": {"fp32": 350846464, "fp64": 203616576}}
 
