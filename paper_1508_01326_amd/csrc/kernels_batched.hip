@@ -467,7 +467,7 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
                 const double shi = hi, slo = lo, sab = ab;
                 const unsigned long long snfb = nfb;
                 const int sg = gcount;
-                const int ntake = shared_round<M, true, kBatchBS>(FJ, bt, L.cf, next, pi1, W, lane, 0ull, hi, lo, ab,
+                const int ntake = shared_round<M, true, kBatchBS>(FJ, bt, L.cf, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab,
                                                                   nfb, gcount, minors);
                 if (gcount > FJ.defer_cap) {
                     // the round's flagged minors do not fit the queue: the round
@@ -478,7 +478,7 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
                     nfb = snfb;
                     gcount = sg;
                     wave_lds_sync();
-                    (void)shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, W, lane, 0ull, hi, lo, ab, nfb,
+                    (void)shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab, nfb,
                                                            gcount, minors);
                     if (lane == 0) nfb += minors;
                 }
@@ -498,7 +498,7 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     // double rounds (FP64, or FP32-bulk under kF32MinMinors minors: every minor
     // counted as done in double)
     while (next < pi1) {
-        const int ntake = shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, W, lane, 0ull, hi, lo, ab, nfb,
+        const int ntake = shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab, nfb,
                                                            gcount, minors);
         if (F32 && lane == 0) nfb += minors;
         next += (unsigned long long)ntake;

@@ -333,16 +333,17 @@ __global__ __launch_bounds__(kMaxBlock) void k_refactor_deferred(FloatJob J, int
                     // the blocks of m-2 column prefixes this wave of the float launch was given
                     const unsigned long long nblk =
                         J.colex ? J.colex_blocks : (J.p_end - J.p_begin + kPrefixBlock - 1) / kPrefixBlock;
-                    // a colex block prefix by prefix, a dictionary block whole
+                    // a two-sided block prefix by prefix (in its side's
+                    // coordinates), a dictionary block whole
                     for (unsigned long long blk = gw; blk < nblk; blk += nw) {
                         unsigned long long t0 = 0;
-                        int segs = 1;
-                        if (J.colex) colex_block<M - 2>(blk, J.n, bt, M, J.colex_pairs, lane, t0, segs);
+                        int segs = 1, side = 0, vlast = 0;
+                        if (J.colex) split_block<M - 2>(blk, J.n, bt, M, J.colex_pairs, lane, side, vlast, t0, segs);
                         for (int sgm = 0; sgm < segs; ++sgm) {
                             unsigned long long r0, r1;
-                            if (J.colex) colex_prefix_ranks<M>(J, bt, t0 + (unsigned long long)sgm, r0, r1);
+                            if (J.colex) split_prefix_ranks<M>(J, bt, side, vlast, t0 + (unsigned long long)sgm, r0, r1);
                             else prefix_block_ranks<M>(J, bt, blk, r0, r1);
-                            redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                            redo_ranks_f64<M>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb, side);
                         }
                     }
                 }

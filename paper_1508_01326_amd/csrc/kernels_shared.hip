@@ -91,12 +91,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
     const unsigned long long nwaves = (unsigned long long)gridDim.x * waves;
 
     for (unsigned long long blk = gwave; blk < nblk && !overflow; blk += nwaves) {
-        // colex blocks (whole rank space) hold colex numbers; otherwise 64
-        // dictionary numbers from p_begin
+        // two-sided blocks (whole rank space) hold prefixes of one side and
+        // last column; otherwise 64 dictionary numbers from p_begin
         unsigned long long next, pi1;
+        int side = 0, vlast = 0;
         if (J.colex) {
             int cnt;
-            colex_block<P>(blk, n, bt, BS, J.colex_pairs, lane, next, cnt);
+            split_block<P>(blk, n, bt, BS, J.colex_pairs, lane, side, vlast, next, cnt);
             pi1 = next + (unsigned long long)cnt;
         } else {
             next = J.p_begin + blk * kPrefixBlock;
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
             [[maybe_unused]] const unsigned long long snfb = nfb;
             [[maybe_unused]] const int sg = gcount;
             unsigned minors;
-            const int ntake = shared_round<M, F32, BS>(J, bt, src, next, pi1, W, lane, gwave, hi, lo, ab, nfb,
+            const int ntake = shared_round<M, F32, BS>(J, bt, src, next, pi1, side, vlast, W, lane, gwave, hi, lo, ab, nfb,
                                                        gcount, minors);
             if constexpr (F32 && shared_tail_refactor(M)) {
                 if (gcount > J.defer_cap) {
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
                     nfb = snfb;
                     gcount = sg;
                     wave_lds_sync();
-                    (void)shared_round<M, false, BS>(J, bt, cd, next, pi1, W, lane, gwave, hi, lo, ab, nfb, gcount,
+                    (void)shared_round<M, false, BS>(J, bt, cd, next, pi1, side, vlast, W, lane, gwave, hi, lo, ab, nfb, gcount,
                                                      minors);
                     if (lane == 0) nfb += minors;
                 }

@@ -195,6 +195,9 @@ __device__ double coop_det_f64(const double* cd, const int (&c)[M], double* W, i
 // A queued minor is 16 bytes: its M 0-based column indices in 10-bit fields,
 // three per 32-bit word (M <= 12, n <= 1024).
 constexpr int kColBits = 10;
+// Bit 31 of an entry's first word: its columns are stored in descending order
+// (the minor's determinant in that order is (-1)^(m(m-1)/2) times its own).
+constexpr unsigned kColsDescending = 1u << 31;
 
 template <int M>
 __device__ __forceinline__ void pack_cols(const int (&col)[M], unsigned (&w)[4]) {
@@ -217,7 +220,7 @@ __device__ __forceinline__ double refactor_entry_f64(const double* cd, const uns
     unpack_cols<M>(entry, c);
     double a[M][M];
     gather_f64<M, ST64>(a, cd, c);
-    bool neg = radic_sign_odd<M>(c);
+    bool neg = radic_sign_odd<M>(c) ^ ((entry[0] & kColsDescending) && ((M * (M - 1) / 2) & 1));
     bool flag = false;
     unsigned long long perm = 0;
     int perm_odd = 0;
@@ -290,7 +293,8 @@ __device__ __forceinline__ double group_refactor_f64(const double* cd, const uns
                                                      double& absdet) {
     int c[M];
     unpack_cols<M>(entry, c);
-    return group_refactor_cols_f64<M, ST64>(cd, c, lane, absdet);
+    const double t = group_refactor_cols_f64<M, ST64>(cd, c, lane, absdet);
+    return ((entry[0] & kColsDescending) && ((M * (M - 1) / 2) & 1)) ? -t : t;
 }
 
 // Refactor queued minors in double, one minor per lane; lane l takes entries

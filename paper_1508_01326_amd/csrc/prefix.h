@@ -147,6 +147,139 @@ __device__ void colex_block(unsigned long long blk, int n, const unsigned long l
     }
 }
 
+// Two-sided blocks (see split_shape).  The side-s prefixes with last column v
+// number sum_{i >= imin} C(a, i) C(b, m-3-i): i of their first m-3 columns lie
+// below a, the others in [a, v).  They are ordered by i, then by the columns
+// in [a, v) (colex), then by those below a (colex), and cut into runs of
+// colex_run(r, K) prefixes.  Blocks go over v upwards, side 0 before side 1
+// for each v (both sides of a v have r = n-1-v later columns), so the heaviest
+// come first and no block spans two values of v or two sides.
+// bt[x*stride + y] = C(x, y) for y <= m-3.
+template <int P>
+__device__ __forceinline__ unsigned long long split_count(int n, int side, int v, const unsigned long long* bt,
+                                                          int stride) {
+    int a, b, imin;
+    bool on;
+    split_shape(P, n, side, v, a, b, imin, on);
+    unsigned long long N = 0;
+    if (on)
+        for (int i = imin; i <= P - 1; ++i) N += bt[a * stride + i] * bt[b * stride + (P - 1 - i)];
+    return N;
+}
+
+// Largest x in [deg-1, lim-1] with C(x, deg) <= t (deg >= 1, t < C(lim, deg)).
+__device__ __forceinline__ int colex_digit(unsigned long long t, int deg, int lim, const unsigned long long* bt,
+                                           int stride) {
+    if (deg == 1) return (int)t;
+    int lo = deg - 1, h = lim - 1;
+    while (lo < h) {
+        const int mid = (lo + h + 1) >> 1;
+        if (bt[mid * stride + deg] <= t) lo = mid;
+        else h = mid - 1;
+    }
+    return lo;
+}
+
+// The j-th side-s prefix with last column v (j < split_count) to its columns
+// c_0 < ... < c_{m-3} = v, in the coordinates of its side.
+template <int P>
+__device__ __forceinline__ void split_unrank(unsigned long long j, int n, int side, int v,
+                                             const unsigned long long* bt, int stride, int (&c)[P]) {
+    int a, b, imin;
+    bool on;
+    split_shape(P, n, side, v, a, b, imin, on);
+    int i = imin;
+    for (; i < P - 1; ++i) {
+        const unsigned long long t = bt[a * stride + i] * bt[b * stride + (P - 1 - i)];
+        if (j < t) break;
+        j -= t;
+    }
+    // j = hi * C(a, i) + lo: hi numbers the columns in [a, v), lo those below a
+    const unsigned long long A = bt[a * stride + i];
+    unsigned long long hi, lo;
+    if ((j >> 32) == 0 && (A >> 32) == 0) {
+        hi = (unsigned)j / (unsigned)A;
+        lo = (unsigned)j - (unsigned)hi * (unsigned)A;
+    } else {
+        hi = j / A;
+        lo = j - hi * A;
+    }
+    int hlim = b, llim = a;
+#pragma unroll
+    for (int k = P - 2; k >= 0; --k) {
+        const bool high = k >= i;
+        const int deg = high ? k - i + 1 : k + 1;
+        const unsigned long long t = high ? hi : lo;
+        const int x = colex_digit(t, deg, high ? hlim : llim, bt, stride);
+        const unsigned long long rest = t - (deg == 1 ? (unsigned long long)x : bt[x * stride + deg]);
+        if (high) {
+            hi = rest;
+            hlim = x;
+            c[k] = a + x;
+        } else {
+            lo = rest;
+            llim = x;
+            c[k] = x;
+        }
+    }
+    c[P - 1] = v;
+}
+
+// Block blk of the two-sided blocks: its side, last column v, first index j0
+// among the side's prefixes with that v, and prefix count (0 past the last
+// block).  The wave's lanes take 32 values of v (two sides each) at a time and
+// scan their block counts; every lane of the wave calls this and gets the same
+// answer.
+template <int P>
+__device__ void split_block(unsigned long long blk, int n, const unsigned long long* bt, int stride, unsigned K,
+                            int lane, int& side, int& v, unsigned long long& j0, int& count) {
+    unsigned long long acc = 0;
+    side = 0;
+    v = P - 1;
+    j0 = 0;
+    count = 0;
+    for (int v0 = P - 1; v0 <= n - 3; v0 += kWave / 2) {
+        const int vv = v0 + lane / 2, sd = lane & 1;
+        unsigned long long nb = 0, cnt = 0;
+        int k = 1;
+        if (vv <= n - 3) {
+            cnt = split_count<P>(n, sd, vv, bt, stride);
+            k = colex_run(n - 1 - vv, K);
+            nb = (cnt + (unsigned long long)k - 1) / (unsigned long long)k;
+        }
+        const unsigned long long incl = wave_scan_u64(nb, lane);
+        const unsigned long long tot = __shfl(incl, kWave - 1, kWave);
+        if (blk < acc + tot) {
+            const bool mine = nb > 0 && blk >= acc + incl - nb && blk < acc + incl;
+            const int owner = __ffsll((long long)__ballot(mine)) - 1;
+            unsigned long long st = 0;
+            int c = 0;
+            if (mine) {
+                st = (blk - (acc + incl - nb)) * (unsigned long long)k;
+                const unsigned long long rem = cnt - st;
+                c = (int)(rem < (unsigned long long)k ? rem : (unsigned long long)k);
+            }
+            // wave-uniform results, kept in scalar registers
+            const unsigned long long sj = __shfl(st, owner, kWave);
+            j0 = ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(sj >> 32)) << 32) |
+                 (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)sj);
+            count = __builtin_amdgcn_readfirstlane(__shfl(c, owner, kWave));
+            side = __builtin_amdgcn_readfirstlane(owner & 1);
+            v = __builtin_amdgcn_readfirstlane(v0 + owner / 2);
+            return;
+        }
+        acc += tot;
+    }
+}
+
+// Column list of a side-s minor, from its side's coordinates (ascending) to the
+// matrix's (ascending): side 1 reads column c as n-1-c.
+template <int M>
+__device__ __forceinline__ void side_to_matrix(const int (&cs)[M], int n, int side, int (&c)[M]) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) c[k] = side ? n - 1 - cs[M - 1 - k] : cs[k];
+}
+
 // Dictionary rank of the first sequence (c, c_{m-3}+1, c_{m-3}+2) of a prefix c
 // of m-2 columns: the sequences after it number sum_k C(n-1-c_k, m-k) (read from
 // the full binomial table).
@@ -252,10 +385,12 @@ __device__ void prefix_block_ranks(const Job& J, const unsigned long long* bt, u
 // natural order, from the row-scaled double copy cd, column stride ST64): lane l
 // takes the l-th of 64 contiguous sub-ranges.  bt[x*BSTRIDE + y] = C(x, y).
 // Counts the ranks in nvalid.
+// With side 1 the ranks are those of the column-reversed matrix (see
+// split_shape) and each minor is evaluated through the matrix's own columns.
 template <int M, int BSTRIDE = M, int ST64 = Layout<M>::st64>
 __device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
                                unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
-                               double& ab, unsigned long long& nvalid) {
+                               double& ab, unsigned long long& nvalid, int side = 0) {
     if (hi <= lo) return;
     const unsigned long long per = (hi - lo + kWave - 1) / kWave;
     const unsigned long long s0 = lo + (unsigned long long)lane * per;
@@ -264,9 +399,11 @@ __device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, 
     int col[M];
     unrank_strided<M>(s0 < hi ? s0 : lo, J.n, bt, BSTRIDE, col);
     for (unsigned long long s = 0; s < per; ++s) {
+        int cm[M];
+        side_to_matrix<M>(col, J.n, side, cm);
         double a[M][M];
-        gather_f64<M, ST64>(a, cd, col);
-        bool neg = radic_sign_odd<M>(col);
+        gather_f64<M, ST64>(a, cd, cm);
+        bool neg = radic_sign_odd<M>(cm);
         bool flag = false;
         unsigned long long perm = 0;
         int perm_odd = 0;
@@ -287,6 +424,20 @@ __device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, 
 // Ranks [r0, r1) of the minors with colex prefix number t (see
 // unrank_prefix_colex), empty past the last prefix.  bt[x*BSTRIDE + y] = C(x, y)
 // for y <= m-2.
+// Ranks [r0, r1), in the coordinates of its side, of the minors of the j-th
+// side-s prefix with last column v (see split_block).  bt[x*BSTRIDE + y] =
+// C(x, y) for y <= m-3.
+template <int M, int BSTRIDE = M>
+__device__ void split_prefix_ranks(const FloatJob& J, const unsigned long long* bt, int side, int v,
+                                   unsigned long long j, unsigned long long& r0, unsigned long long& r1) {
+    constexpr int P = M - 2;
+    int c[P];
+    split_unrank<P>(j, J.n, side, v, bt, BSTRIDE, c);
+    const int r = J.n - 1 - v;
+    r0 = prefix_first_rank<M>(c, J.n, J.total);
+    r1 = r0 + (unsigned long long)(r * (r - 1) / 2);
+}
+
 template <int M, int BSTRIDE = M>
 __device__ void colex_prefix_ranks(const FloatJob& J, const unsigned long long* bt, unsigned long long t,
                                    unsigned long long& r0, unsigned long long& r1) {

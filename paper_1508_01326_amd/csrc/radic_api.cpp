@@ -352,6 +352,31 @@ static unsigned long long colex_block_count(int m, int n, unsigned K) {
     return total;
 }
 
+// Number of two-sided blocks (the kernels' split_block): per last column v and
+// side s, split_count prefixes in runs of colex_run(n-1-v, K).
+static unsigned long long split_block_count(int m, int n, unsigned K) {
+    const int P = m - 2;
+    unsigned long long total = 0;
+    for (int v = P - 1; v <= n - 3; ++v) {
+        const unsigned long long k = (unsigned long long)colex_run(n - 1 - v, K);
+        for (int side = 0; side < 2; ++side) {
+            int a, b, imin;
+            bool on;
+            split_shape(P, n, side, v, a, b, imin, on);
+            if (!on) continue;
+            unsigned long long cnt = 0;
+            for (int i = imin; i <= P - 1; ++i) {
+                unsigned long long x = 0, y = 0;
+                host_binomial(a, i, &x);
+                host_binomial(b, P - 1 - i, &y);
+                cnt += x * y;
+            }
+            total += (cnt + k - 1) / k;
+        }
+    }
+    return total;
+}
+
 // ---------------------------------------------------------------- validation helpers
 static int check_workspace(void* ws, size_t bytes, size_t need) {
     if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255u) || bytes < need) return RADIC_EWORKSPACE;
@@ -581,10 +606,11 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
             J.mapping = 0;
         } else {
             sh.block = block;
-            // a whole rank space takes its prefixes in colex blocks (heaviest first)
+            // a whole rank space takes its prefixes in two-sided blocks
+            // (heaviest first)
             J.colex = (kt == 2 && J.p_begin == 0 && J.p_end == J.n_prefix) ? 1 : 0;
             J.colex_pairs = 64u * (unsigned)(sh.spl_set ? sh.spl : kSharedSplFloat);
-            J.colex_blocks = J.colex ? colex_block_count(m, n, J.colex_pairs) : 0;
+            J.colex_blocks = J.colex ? split_block_count(m, n, J.colex_pairs) : 0;
             const unsigned long long per_block = kt == 2 ? kPrefixBlock : kGroupBlock;
             const unsigned long long blocks =
                 J.colex ? J.colex_blocks : (J.p_end - J.p_begin + per_block - 1) / per_block;

@@ -28,6 +28,32 @@ __host__ __device__ inline int colex_run(int r, unsigned K) {
     const unsigned k = pairs ? K / pairs : (unsigned)kPrefixBlock;
     return k < 1u ? 1 : (k > (unsigned)kPrefixBlock ? kPrefixBlock : (int)k);
 }
+// Two-sided prefix sharing over a whole rank space.  A minor with columns
+// j_0 < ... < j_{m-1} can share its first m-2 columns with the minors that
+// differ only in the last two (side 0: r = n-1-j_{m-3} free columns after
+// them), or its last m-2 columns with those that differ only in the first two
+// (side 1: j_2 free columns before them).  Each minor goes to the side with
+// more free columns (side 0 on a tie).  Side 1 is side 0 of the column-reversed
+// matrix (column c read as n-1-c): there a minor's shared columns come first
+// again, and with m >= 5 both choices depend only on the shared columns, so a
+// side-s prefix c_0 < ... < c_{m-3} (last column v, r = n-1-v) is taken
+// exactly when c_2 <= r - s.  Below m = 5 every prefix is on side 0.
+// The side-s prefixes with last column v: their other m-3 columns hold at
+// least `imin` below a and the rest in [a, v); `on` false when there are none.
+__host__ __device__ inline void split_shape(int P, int n, int side, int v, int& a, int& b, int& imin, bool& on) {
+    const int L = n - 1 - v - side;   // largest admissible c_2
+    if (P >= 4) {
+        a = L + 1 < v ? L + 1 : v;
+        b = v - a;
+        imin = 3;
+        on = true;
+    } else {
+        a = v;
+        b = 0;
+        imin = P - 1;
+        on = P == 3 ? v <= L : side == 0;
+    }
+}
 // FP32-bulk in the shared kernels: up to m = 8 a workgroup refactors its
 // flagged minors in double when its waves are done (eight lanes per minor, one
 // row each); above, the refactorisation kernel does it.
@@ -90,8 +116,9 @@ struct FloatJob {
     unsigned long long n_prefix;  // C(n-2, m-2) (mapping 1) or C(n-3, m-3) (mapping 2)
     unsigned long long p_begin;   // prefixes [p_begin, p_end) cover [q_begin, q_begin + count)
     unsigned long long p_end;
-    // Mapping 1 over the whole rank space: 1 when the blocks are colex blocks
-    // (consecutive prefixes in colex order, last column first, about
+    // Mapping 1 over the whole rank space: 1 when the blocks are two-sided
+    // blocks (split_block: each minor shared through its first or its last m-2
+    // columns, blocks of prefixes with one last column and side, about
     // colex_pairs minors each, heaviest first; colex_blocks of them), 0 when
     // block blk holds the prefixes p_begin + blk*64 ... in dictionary order.
     int colex;

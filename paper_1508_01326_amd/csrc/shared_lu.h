@@ -106,11 +106,12 @@ __device__ __forceinline__ void left_steps(T (&L)[M][P], const T* src, int strid
 // per-lane matrix): group g takes the g-th of 64/G contiguous sub-ranges,
 // unranks its first sequence (Section 4) and walks the rest with the successor
 // (Section 5); its first lane adds the terms.  bt[x*BS + y] = C(x, y).  Counts
-// the ranks in nvalid.
+// the ranks in nvalid.  With side 1 the ranks are those of the column-reversed
+// matrix (see split_shape), each minor evaluated through the matrix's columns.
 template <int M, int BS, int S64>
 __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long* bt, const double* cd,
                                      unsigned long long lo, unsigned long long hi, int lane, double& h, double& l,
-                                     double& ab, unsigned long long& nvalid) {
+                                     double& ab, unsigned long long& nvalid, int side = 0) {
     constexpr int G = refactor_group<M>(), NG = kWave / G;
     if (hi <= lo) return;
     const int g = lane / G;
@@ -120,8 +121,10 @@ __device__ void redo_ranks_group_f64(const FloatJob& J, const unsigned long long
     int col[M];
     unrank_strided<M>(s0 < hi ? s0 : lo, J.n, bt, BS, col);
     for (unsigned long long s = 0; s < per; ++s) {
+        int cm[M];
+        side_to_matrix<M>(col, J.n, side, cm);
         double ad;
-        const double term = group_refactor_cols_f64<M, S64>(cd, col, lane, ad);
+        const double term = group_refactor_cols_f64<M, S64>(cd, cm, lane, ad);
         if (s0 + s < s1 && (lane & (G - 1)) == 0) {
             double sum, err;
             two_sum(h, term, sum, err);
@@ -184,8 +187,8 @@ __device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned lo
 // FP32-bulk tail of a prefix-shared workgroup.  Each wave queued its flagged
 // minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
 // segment overflowed drops its float sums and redoes its own blocks (BLOCK
-// prefixes of m-KT columns: gwave, gwave + nwaves, ...; colex blocks prefix by
-// prefix) in double, a group of refactor_group<M>() lanes per minor.  The
+// prefixes of m-KT columns: gwave, gwave + nwaves, ...; two-sided blocks prefix
+// by prefix) in double, a group of refactor_group<M>() lanes per minor.  The
 // entries of the other waves are pooled and refactored in double by such groups
 // of the workgroup's threads, in a fixed order (group g takes entries g, g + NG,
 // ...; its first lane adds the term).  segn: a workgroup LDS array of 16.  Every thread of the workgroup calls this.  Reads the binomial
@@ -200,19 +203,20 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
     if (gcount > J.defer_cap) {
         hi = lo = ab = 0.0;
         nfb = 0;
-        // one contiguous rank range per step: a dictionary block whole, a colex
-        // block prefix by prefix (one call site keeps the registers of this cold
-        // path within those of the main loop)
+        // one contiguous rank range per step: a dictionary block whole, a
+        // two-sided block prefix by prefix, in its side's coordinates (one call
+        // site keeps the registers of this cold path within those of the main
+        // loop)
         const bool colex = KT == 2 && J.colex;
         for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
             unsigned long long t0 = 0;
-            int segs = 1;
-            if (colex) colex_block<M - 2>(blk, J.n, bt, BS, J.colex_pairs, lane, t0, segs);
+            int segs = 1, side = 0, vlast = 0;
+            if (colex) split_block<M - 2>(blk, J.n, bt, BS, J.colex_pairs, lane, side, vlast, t0, segs);
             for (int sgm = 0; sgm < segs; ++sgm) {
                 unsigned long long r0, r1;
-                if (colex) colex_prefix_ranks<M, BS>(J, bt, t0 + (unsigned long long)sgm, r0, r1);
+                if (colex) split_prefix_ranks<M, BS>(J, bt, side, vlast, t0 + (unsigned long long)sgm, r0, r1);
                 else prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
-                redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
+                redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb, side);
             }
         }
     }

@@ -64,8 +64,10 @@ struct RoundLds {
 // later columns after each prefix, dictionary order) are split evenly over the
 // lanes, each a 2 x 2 determinant times its prefix's signed pivot product.
 // J supplies n, the rank window [q_begin, q_begin + count) of C(n, m) = total
-// (prefixes clipped to it; with J.colex the prefixes are colex numbers of a
-// whole rank space), n_prefix, the slot count cap and, for FP32-bulk, tau and
+// (prefixes clipped to it; with J.colex the prefixes are those numbered next ...
+// among the side-`side` prefixes with last column vlast of a whole rank space,
+// see split_block, and side 1 reads the matrix with its columns reversed),
+// n_prefix, the slot count cap and, for FP32-bulk, tau and
 // the segment of J.fb_entries (defer_cap entries from gwave * defer_cap).  Adds the
 // round's terms to (hi, lo, ab); FP32-bulk queues its flagged minors in the
 // wave's segment of J.fb_entries (nfb, gcount; gcount wave-uniform on return).
@@ -73,8 +75,9 @@ struct RoundLds {
 template <int M, bool F32, int BS>
 __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned long long* bt,
                                             const typename std::conditional<F32, float, double>::type* src,
-                                            unsigned long long next, unsigned long long pi1, const RoundLds& W,
-                                            int lane, unsigned long long gwave, double& hi, double& lo, double& ab,
+                                            unsigned long long next, unsigned long long pi1, int side, int vlast,
+                                            const RoundLds& W, int lane, unsigned long long gwave, double& hi,
+                                            double& lo, double& ab,
                                             unsigned long long& nfb, int& gcount, unsigned& minors) {
     using T = typename std::conditional<F32, float, double>::type;
     using TV = typename std::conditional<F32, float4, double2>::type;
@@ -99,15 +102,9 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
     const unsigned long long pi = next + lane;
     const bool have = pi < pi1;
     int c[P];
-    if (J.colex) unrank_prefix_colex<P>(have ? pi : next, n, bt, BS, c);
+    if (J.colex) split_unrank<P>(have ? pi : next, n, side, vlast, bt, BS, c);
     else unrank_prefix<P>(have ? pi : next, n, J.n_prefix, bt, BS, c);
     const int r = n - 1 - c[P - 1];
-    // dictionary rank of the prefix's first sequence (c, c_{m-3}+1, c_{m-3}+2):
-    // the sequences after it number sum_k C(n-1-c_k, m-k)
-    unsigned long long after = bt[(r - 1) * BS + 2] + bt[(r - 2) * BS + 1];
-#pragma unroll
-    for (int k = 0; k < P; ++k) after += bt[(n - 1 - c[k]) * BS + (M - k)];
-    const unsigned long long base = J.total - 1 - after;
     // projected-column slots: lanes take prefixes while the slots last
     // (lane 0 always fits: cap >= n - m + 2 >= r)
     const unsigned rs = wave_scan_u32(have ? (unsigned)r : 0u, lane);
@@ -115,17 +112,29 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
     const int ntake = __popcll(__ballot(take));
     const unsigned ncols = __shfl(rs, ntake - 1, kWave);
     const unsigned cnt = take ? (unsigned)(r * (r - 1) / 2) : 0u;
-    // the prefix's pairs inside [q_begin, q_begin + count)
+    // the prefix's pairs inside [q_begin, q_begin + count) (all of them over a
+    // whole rank space)
     unsigned lo_c = 0, hi_c = cnt;
-    if (base < J.q_begin) {
-        const unsigned long long d = J.q_begin - base;
-        lo_c = d < cnt ? (unsigned)d : cnt;
+    if (!J.colex) {
+        // dictionary rank of the prefix's first sequence (c, c_{m-3}+1,
+        // c_{m-3}+2): the sequences after it number sum_k C(n-1-c_k, m-k)
+        unsigned long long after = bt[(r - 1) * BS + 2] + bt[(r - 2) * BS + 1];
+#pragma unroll
+        for (int k = 0; k < P; ++k) after += bt[(n - 1 - c[k]) * BS + (M - k)];
+        const unsigned long long base = J.total - 1 - after;
+        if (base < J.q_begin) {
+            const unsigned long long d = J.q_begin - base;
+            lo_c = d < cnt ? (unsigned)d : cnt;
+        }
+        if (base + cnt > qend) {
+            const unsigned long long d = qend > base ? qend - base : 0ull;
+            hi_c = d < cnt ? (unsigned)d : cnt;
+        }
+        if (hi_c < lo_c) hi_c = lo_c;
     }
-    if (base + cnt > qend) {
-        const unsigned long long d = qend > base ? qend - base : 0ull;
-        hi_c = d < cnt ? (unsigned)d : cnt;
-    }
-    if (hi_c < lo_c) hi_c = lo_c;
+    // from here on c holds the matrix's columns: side 1 reads column c as n-1-c
+#pragma unroll
+    for (int k = 0; k < P; ++k) c[k] = side ? n - 1 - c[k] : c[k];
     const unsigned cc = hi_c - lo_c;
     const unsigned ccincl = wave_scan_u32(cc, lane);
     const unsigned Tr = __shfl(ccincl, kWave - 1, kWave);
@@ -155,8 +164,11 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
             pz1[k] = s1;
         }
         prel = rel;
-        // sign: the lane's exchanges and the prefix's share of (-1)^(r+s)
-        int ps = M * (M + 1) / 2 + P;
+        // sign: the lane's exchanges and the prefix's share of (-1)^(r+s) in
+        // its side's coordinates (whose column sum has the parity of
+        // side * P(n-1) + sum c); on side 1 a term of the reversed matrix is
+        // (-1)^(m(m-1)/2 + m(n+1)) times the matrix's own
+        int ps = M * (M + 1) / 2 + P + (side ? M * (M - 1) / 2 + M * (n + 1) + P * (n - 1) : 0);
 #pragma unroll
         for (int k = 0; k < P; ++k) ps += c[k];
         const bool sg = neg ^ ((ps & 1) != 0);
@@ -170,7 +182,9 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
             cincl[lane] = rs;
             if (F32) {
                 ratios[lane] = ratio;
-                uint4 w = make_uint4(0u, 0u, 0u, 0u);
+                // the matrix's columns; a side-1 minor's are stored in
+                // descending order, marked by bit 31 of the first word
+                uint4 w = make_uint4(side ? kColsDescending : 0u, 0u, 0u, 0u);
 #pragma unroll
                 for (int k = 0; k < P; ++k) {
                     const unsigned v = (unsigned)c[k] << (kColBits * (k % 3));
@@ -236,7 +250,8 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
             }
             if (act) {
                 // slot g holds column c_{m-3} + 1 + (g - sbeg) = n - send + g
-                const T* colp = src + (n - (int)send + (int)g) * ST;
+                // (the matrix's column n-1-(n-send+g) on side 1)
+                const T* colp = src + (side ? (int)send - (int)g - 1 : n - (int)send + (int)g) * ST;
                 T t0, t1;
                 project<M, P, T>(z0, z1, off, colp, t0, t1);
                 // (-1)^j folded in for the j-th column after the prefix
@@ -347,7 +362,8 @@ __device__ __forceinline__ int shared_round(const FloatJob& J, const unsigned lo
                                                  (unsigned)(fm >> 32),
                                                  __builtin_amdgcn_mbcnt_lo((unsigned)fm, 0u));
                     if (flag && pos < J.defer_cap) {
-                        const int ca = n - hr + ia, cbb = n - hr + ib;
+                        const int ca = side ? hr - 1 - ia : n - hr + ia;
+                        const int cbb = side ? hr - 1 - ib : n - hr + ib;
                         const uint4 pw = wcols[s];
                         unsigned w[4] = {pw.x, pw.y, pw.z, pw.w};
                         w[P / 3] |= (unsigned)ca << (kColBits * (P % 3));
