@@ -104,27 +104,34 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_shared(FloatJob J) {
             const unsigned long long pe = next + kPrefixBlock;
             pi1 = pe < J.p_end ? pe : J.p_end;
         }
+        // prefixes a round may take: halved while its flagged minors overflow
+        // the segment (FP32-bulk up to m = 8)
+        int limit = kPrefixBlock;
         while (next < pi1 && !overflow) {
             [[maybe_unused]] const double shi = hi, slo = lo, sab = ab;
             [[maybe_unused]] const unsigned long long snfb = nfb;
             [[maybe_unused]] const int sg = gcount;
             unsigned minors;
-            const int ntake = shared_round<M, F32, BS>(J, bt, src, next, pi1, side, vlast, W, lane, gwave, hi, lo, ab, nfb,
-                                                       gcount, minors);
+            const unsigned long long lend = next + (unsigned long long)limit;
+            const int ntake = shared_round<M, F32, BS>(J, bt, src, next, lend < pi1 ? lend : pi1, side, vlast, W, lane,
+                                                       gwave, hi, lo, ab, nfb, gcount, minors);
             if constexpr (F32 && shared_tail_refactor(M)) {
                 if (gcount > J.defer_cap) {
                     // the round's flagged minors do not fit the segment: the
-                    // round again, in double (every one of its minors counted
-                    // as refactored)
+                    // round again over half as many prefixes, or, for a single
+                    // prefix, its minors each in double by a lane group (and
+                    // counted as refactored)
                     hi = shi;
                     lo = slo;
                     ab = sab;
                     nfb = snfb;
                     gcount = sg;
                     wave_lds_sync();
-                    (void)shared_round<M, false, BS>(J, bt, cd, next, pi1, side, vlast, W, lane, gwave, hi, lo, ab, nfb, gcount,
-                                                     minors);
-                    if (lane == 0) nfb += minors;
+                    if (ntake > 1) {
+                        limit = (ntake + 1) / 2;
+                        continue;
+                    }
+                    redo_round_groups<M, BS, S64>(J, bt, cd, next, 1, side, vlast, lane, hi, lo, ab, nfb);
                 }
             } else {
                 // a full segment: the wave's blocks are redone in double (by the

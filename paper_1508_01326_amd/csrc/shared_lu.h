@@ -161,6 +161,31 @@ __device__ void refactor_queue_groups(const double* cd, const uint4* q, int coun
     }
 }
 
+// FP32-bulk, prefix-shared: every minor of one round (the prefixes next ...
+// next + ntake - 1, of a two-sided block or dictionary numbers, clipped to the
+// call's rank window) refactored in double by the wave's lane groups, each
+// counted in nvalid.  Used when a round flags more minors than the wave's
+// segment holds.  Every lane calls this.
+template <int M, int BS, int S64>
+__device__ void redo_round_groups(const FloatJob& J, const unsigned long long* bt, const double* cd,
+                                  unsigned long long next, int ntake, int side, int vlast, int lane, double& hi,
+                                  double& lo, double& ab, unsigned long long& nvalid) {
+    if (J.colex) {
+        for (int t = 0; t < ntake; ++t) {
+            unsigned long long r0, r1;
+            split_prefix_ranks<M, BS>(J, bt, side, vlast, next + (unsigned long long)t, r0, r1);
+            redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nvalid, side);
+        }
+    } else {
+        unsigned long long r0 = first_completion_rank<M, FloatJob, 2>(next, J, bt, BS);
+        unsigned long long r1 = first_completion_rank<M, FloatJob, 2>(next + (unsigned long long)ntake, J, bt, BS);
+        const unsigned long long qe = J.q_begin + J.count;
+        if (r0 < J.q_begin) r0 = J.q_begin;
+        if (r1 > qe) r1 = qe;
+        redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nvalid, 0);
+    }
+}
+
 // FP32-bulk, between two rounds of a prefix-shared wave: when the wave's segment
 // of J.fb_entries is more than half full (gcount entries, wave-uniform), the
 // wave refactors them in double here, in whole passes of its lane groups
@@ -185,10 +210,12 @@ __device__ void relieve_segment(const FloatJob& J, const double* cd, unsigned lo
 }
 
 // FP32-bulk tail of a prefix-shared workgroup.  Each wave queued its flagged
-// minors in its segment of J.fb_entries (gcount, wave-uniform).  A wave whose
-// segment overflowed drops its float sums and redoes its own blocks (BLOCK
-// prefixes of m-KT columns: gwave, gwave + nwaves, ...; two-sided blocks prefix
-// by prefix) in double, a group of refactor_group<M>() lanes per minor.  The
+// minors in its segment of J.fb_entries (gcount, wave-uniform).  With m-3
+// column prefixes (KT = 3) a wave whose segment overflowed drops its float sums
+// and redoes its own blocks (BLOCK prefixes: gwave, gwave + nwaves, ...) in
+// double, a group of refactor_group<M>() lanes per minor; with m-2 column
+// prefixes a round that would overflow is redone at once (redo_round_groups),
+// so no segment overflows.  The
 // entries of the other waves are pooled and refactored in double by such groups
 // of the workgroup's threads, in a fixed order (group g takes entries g, g + NG,
 // ...; its first lane adds the term).  segn: a workgroup LDS array of 16.  Every thread of the workgroup calls this.  Reads the binomial
@@ -200,23 +227,15 @@ __device__ void shared_fp32_tail(const FloatJob& J, const unsigned long long* bt
     const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     if (lane == 0) segn[wave] = (unsigned)gcount;
     __syncthreads();
-    if (gcount > J.defer_cap) {
-        hi = lo = ab = 0.0;
-        nfb = 0;
-        // one contiguous rank range per step: a dictionary block whole, a
-        // two-sided block prefix by prefix, in its side's coordinates (one call
-        // site keeps the registers of this cold path within those of the main
-        // loop)
-        const bool colex = KT == 2 && J.colex;
-        for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
-            unsigned long long t0 = 0;
-            int segs = 1, side = 0, vlast = 0;
-            if (colex) split_block<M - 2>(blk, J.n, bt, BS, J.colex_pairs, lane, side, vlast, t0, segs);
-            for (int sgm = 0; sgm < segs; ++sgm) {
+    if constexpr (KT == 3) {
+        if (gcount > J.defer_cap) {
+            hi = lo = ab = 0.0;
+            nfb = 0;
+            // one contiguous rank range per block
+            for (unsigned long long blk = gwave; blk < nblk; blk += nwaves) {
                 unsigned long long r0, r1;
-                if (colex) split_prefix_ranks<M, BS>(J, bt, side, vlast, t0 + (unsigned long long)sgm, r0, r1);
-                else prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
-                redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb, side);
+                prefix_block_ranks<M, FloatJob, KT, BLOCK>(J, bt, blk, r0, r1, BS);
+                redo_ranks_group_f64<M, BS, S64>(J, bt, cd, r0, r1, lane, hi, lo, ab, nfb);
             }
         }
     }

@@ -193,6 +193,38 @@ def test_fallback_forced_each_m(m):
     assert_close(got["abs_sum"], ref["abs_sum"], ref["abs_sum"], 1e-12, "abs_sum")
 
 
+_REF_8X40 = {}
+
+
+def ref_8x40():
+    # 76.9 M minors: the oracle takes a few seconds, so both modes share it
+    if not _REF_8X40:
+        A = workloads.random_float(8, 40, seed=99840)
+        _REF_8X40["A"] = A
+        _REF_8X40["ref"] = oracle.radic_f64(A)
+    return _REF_8X40["A"], _REF_8X40["ref"]
+
+
+def test_fallback_round_overflow():
+    # 8 x 40 over the whole rank space: about 21,000 waves share the deferral
+    # entries, some 200 each.  With tau = 2^-10 some rounds flag more minors
+    # than that and are done again over fewer prefixes; with tau = inf every
+    # round overflows, down to single prefixes whose minors (up to C(34, 2))
+    # outnumber the segment and are refactored in double by lane groups.
+    A, ref = ref_8x40()
+    S = normaliser(ref["abs_sum"], A)
+    got = run(A, "fp64", "8x40 fp64")
+    assert_close(got["value"], ref["value"], S, TOL["fp64"], "8x40 fp64")
+    got = run(A, "fp32_bulk", "8x40 tau=2^-10")
+    assert_close(got["value"], ref["value"], S, TOL["fp32_bulk"], "8x40 tau=2^-10")
+    assert 0 < got["n_fallback"] < math.comb(40, 8) // 50
+    radic.set_fallback_tau(float("inf"))
+    got = run(A, "fp32_bulk", "8x40 tau=inf")
+    assert got["n_fallback"] == math.comb(40, 8)
+    assert_close(got["value"], ref["value"], S, TOL["fp64"], "8x40 tau=inf")
+    assert_close(got["abs_sum"], ref["abs_sum"], ref["abs_sum"], 1e-12, "8x40 tau=inf abs_sum")
+
+
 def test_fallback_near_parallel_columns():
     rng = np.random.default_rng(89)
     A = rng.standard_normal((6, 20))
