@@ -85,13 +85,31 @@ def executed_flops(m, n, enumeration):
     per_prefix = gepp_flops(m, P, P) + kt * P * (P - 1) + P
     flops = 0
     for v in range(P - 1, n - kt):           # last prefix column (0-based)
-        k = math.comb(v, P - 1)              # prefixes ending at v
         r = n - 1 - v                        # columns after it
         if kt == 2:
+            # two-sided blocks: the prefixes ending at v on either side
+            k = split_prefix_count(P, n, 0, v) + split_prefix_count(P, n, 1, v)
             flops += k * (per_prefix + 4 * P * r + 4 * math.comb(r, 2))
         else:
+            k = math.comb(v, P - 1)          # prefixes ending at v
             flops += k * (per_prefix + 6 * P * r + 9 * math.comb(r, 2) + 6 * math.comb(r, 3))
     return flops
+
+
+def split_prefix_count(P, n, side, v):
+    """Prefixes of P = m - 2 columns ending at column v on one side of the
+    prefix-shared kernels' two-sided blocks over a whole rank space: a minor is
+    shared through its first m - 2 columns (side 0) when at least as many
+    columns follow them as precede its last m - 2 (side 1, the same in the
+    column-reversed matrix), so a side-s prefix c is taken when c_2 <= r - s,
+    r = n - 1 - v; below m = 5 every prefix is on side 0."""
+    if P <= 2:
+        return math.comb(v, P - 1) if side == 0 else 0
+    L = n - 1 - v - side
+    if P == 3:
+        return math.comb(v, 2) if v <= L else 0
+    a = min(L + 1, v)
+    return sum(math.comb(a, i) * math.comb(v - a, P - 1 - i) for i in range(3, P))
 
 
 def host_info():

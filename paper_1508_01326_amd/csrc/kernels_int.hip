@@ -166,7 +166,7 @@ struct IntSharedJob {
     int grid_x;
     unsigned long long q_begin, count, total, n_prefix, p_begin, p_end;
     double* partials;             // [prime][grid_x] residues
-    int colex;                    // 1: colex blocks of the whole rank space (see colex_block)
+    int colex;                    // 1: two-sided blocks of the whole rank space (see split_block)
     unsigned colex_pairs;
     unsigned long long colex_blocks;
 };
@@ -211,12 +211,12 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
         unsigned long long next = J.p_begin + blk * kPrefixBlock;
         unsigned long long pi1 = next + kPrefixBlock < J.p_end ? next + kPrefixBlock : J.p_end;
         if (J.colex) {
-            int cnt;
-            colex_block<M - 2>(blk, n, bt, M, J.colex_pairs, lane, next, cnt);
+            int cnt, side, vlast;
+            split_block<M - 2>(blk, n, bt, M, J.colex_pairs, lane, side, vlast, next, cnt);
             pi1 = next + (unsigned long long)cnt;
-            // colex blocks come heaviest first (prefixes with the most later columns)
+            // two-sided blocks come heaviest first (prefixes with the most later columns)
             int_prefix_range<M, true>(cr, n, bt, M, next, pi1, J.n_prefix, 0ull, 0ull, J.total, p, pinv, J.cap,
-                                      slot, incl, tv, lane, acc);
+                                      slot, incl, tv, lane, acc, side, vlast);
         } else {
             unsigned long long r0, r1;
             prefix_block_ranks<M>(J, bt, blk, r0, r1);

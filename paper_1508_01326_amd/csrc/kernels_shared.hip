@@ -7,9 +7,12 @@
 // Those steps are done once per prefix here; what is left of each minor is the
 // last two steps on a 2 x 2 block.
 //
-// A wave takes a block of 64 consecutive prefixes (in colex order for a whole
-// rank space, which puts the prefixes with the most later columns first, or in
-// dictionary order for a rank range) and works in rounds:
+// A wave takes a block of up to 64 prefixes and works in rounds.  Over a whole
+// rank space each minor is shared either through its first m-2 columns or,
+// when fewer columns follow those than precede its last m-2, through its last
+// m-2 (the same scheme on the column-reversed matrix, see split_shape); blocks
+// hold prefixes of one side with one last column and come heaviest first.  A
+// rank range takes 64 consecutive prefixes in dictionary order.  A round:
 //  A. Each lane takes one prefix and factors the m x (m-2) block of its columns
 //     by LU with partial pivoting in registers, column by column (the first m-2
 //     steps of every minor with that prefix).  From the multipliers it forms

@@ -51,51 +51,6 @@ __device__ __forceinline__ void unrank_prefix(unsigned long long pi, int n, unsi
     }
 }
 
-// Prefix number t in the colex order of the (m-2)-subsets of the first n-2
-// columns to its columns c_0 < ... < c_{m-3}: the combinatorial number system
-// t = sum_k C(c_k, k+1), so c_{m-3} is the largest x with C(x, m-2) <= t, and so
-// on downwards (a binary search over the LDS binomial slice bt[x*stride + y] =
-// C(x, y) for the leading digits, closed forms for the last two).  Colex order
-// sorts prefixes by their last column first, so the number of later columns
-// r = n-1-c_{m-3} never grows along it: blocks of consecutive colex numbers
-// come heaviest first and hold prefixes of nearly equal r.
-template <int P>
-__device__ __forceinline__ void unrank_prefix_colex(unsigned long long t, int n, const unsigned long long* bt,
-                                                    int stride, int (&c)[P]) {
-    int hi = n - 3;
-#pragma unroll
-    for (int k = P - 1; k >= 0; --k) {
-        const int j = k + 1;
-        int x;
-        if (j == 1) {
-            x = (int)t;
-        } else if (j == 2) {
-            x = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
-            if ((unsigned long long)x * (unsigned long long)(x - 1) / 2 > t) --x;
-            if ((unsigned long long)(x + 1) * (unsigned long long)x / 2 <= t) ++x;
-            if (x > hi) x = hi;
-            t -= (unsigned long long)x * (unsigned long long)(x - 1) / 2;
-        } else {
-            int lo = j - 1, h = hi;
-            while (lo < h) {
-                const int mid = (lo + h + 1) >> 1;
-                if (bt[mid * stride + j] <= t) lo = mid;
-                else h = mid - 1;
-            }
-            x = lo;
-            t -= bt[x * stride + j];
-        }
-        c[k] = x;
-        hi = x - 1;
-    }
-}
-
-// Colex blocks.  The prefixes with last column v number C(v, m-3) and hold
-// colex numbers C(v, m-2) ... C(v+1, m-2) - 1; each has r = n-1-v later columns
-// and C(r, 2) minors.  They are cut into runs of colex_run(r, K) consecutive
-// prefixes (about K minors per run, at most kPrefixBlock prefixes): a block is
-// one run, blocks go over v upwards (r downwards, so the heaviest come first),
-// and no block spans two values of v.
 // Inclusive scan over the wave of 64-bit counts.
 __device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v, int lane) {
 #pragma unroll
@@ -104,47 +59,6 @@ __device__ __forceinline__ unsigned long long wave_scan_u64(unsigned long long v
         if (lane >= off) v += u;
     }
     return v;
-}
-
-// Block blk of the colex blocks of prefixes of P = m-2 columns out of the first
-// n-2: its first colex number and its prefix count (count 0 past the last
-// block).  The wave's lanes take 64 values of v at a time and scan their block
-// counts; every lane of the wave calls this and gets the same answer.
-// bt[x*stride + y] = C(x, y) for y <= P.
-template <int P>
-__device__ void colex_block(unsigned long long blk, int n, const unsigned long long* bt, int stride, unsigned K,
-                            int lane, unsigned long long& start, int& count) {
-    unsigned long long acc = 0;
-    start = 0;
-    count = 0;
-    for (int v0 = P - 1; v0 <= n - 3; v0 += kWave) {
-        const int v = v0 + lane;
-        unsigned long long nb = 0, cnt = 0;
-        int k = 1;
-        if (v <= n - 3) {
-            cnt = bt[v * stride + (P - 1)];   // C(v, P-1)
-            k = colex_run(n - 1 - v, K);
-            nb = (cnt + (unsigned long long)k - 1) / (unsigned long long)k;
-        }
-        const unsigned long long incl = wave_scan_u64(nb, lane);
-        const unsigned long long tot = __shfl(incl, kWave - 1, kWave);
-        if (blk < acc + tot) {
-            const bool mine = nb > 0 && blk >= acc + incl - nb && blk < acc + incl;
-            const int owner = __ffsll((long long)__ballot(mine)) - 1;
-            unsigned long long st = 0;
-            int c = 0;
-            if (mine) {   // v <= n-3 and j0 < cnt on the owner lane
-                const unsigned long long j0 = (blk - (acc + incl - nb)) * (unsigned long long)k;
-                st = bt[v * stride + P] + j0;   // C(v, P) + j0
-                const unsigned long long rem = cnt - j0;
-                c = (int)(rem < (unsigned long long)k ? rem : (unsigned long long)k);
-            }
-            start = __shfl(st, owner, kWave);
-            count = __shfl(c, owner, kWave);
-            return;
-        }
-        acc += tot;
-    }
 }
 
 // Two-sided blocks (see split_shape).  The side-s prefixes with last column v
@@ -421,9 +335,6 @@ __device__ void redo_ranks_f64(const FloatJob& J, const unsigned long long* bt, 
     }
 }
 
-// Ranks [r0, r1) of the minors with colex prefix number t (see
-// unrank_prefix_colex), empty past the last prefix.  bt[x*BSTRIDE + y] = C(x, y)
-// for y <= m-2.
 // Ranks [r0, r1), in the coordinates of its side, of the minors of the j-th
 // side-s prefix with last column v (see split_block).  bt[x*BSTRIDE + y] =
 // C(x, y) for y <= m-3.
@@ -434,19 +345,6 @@ __device__ void split_prefix_ranks(const FloatJob& J, const unsigned long long* 
     int c[P];
     split_unrank<P>(j, J.n, side, v, bt, BSTRIDE, c);
     const int r = J.n - 1 - v;
-    r0 = prefix_first_rank<M>(c, J.n, J.total);
-    r1 = r0 + (unsigned long long)(r * (r - 1) / 2);
-}
-
-template <int M, int BSTRIDE = M>
-__device__ void colex_prefix_ranks(const FloatJob& J, const unsigned long long* bt, unsigned long long t,
-                                   unsigned long long& r0, unsigned long long& r1) {
-    constexpr int P = M - 2;
-    r0 = r1 = 0;
-    if (t >= J.n_prefix) return;
-    int c[P];
-    unrank_prefix_colex<P>(t, J.n, bt, BSTRIDE, c);
-    const int r = J.n - 1 - c[P - 1];
     r0 = prefix_first_rank<M>(c, J.n, J.total);
     r1 = r0 + (unsigned long long)(r * (r - 1) / 2);
 }

@@ -217,10 +217,10 @@ struct Shape {
     int block;
     bool spl_set = false;   // spl tuned or forced (not the default)
 };
-// Prefix-shared paths: about 64 * spl minors per colex block (subsets per lane
-// per block); their default spl.
+// Prefix-shared paths: about 64 * spl minors per block of a whole rank space
+// (subsets per lane per block); their default spl.
 constexpr int kSharedSplFloat = 64;
-constexpr int kSharedSplInt = 48;
+constexpr int kSharedSplInt = 32;
 // Tuned launch shapes, (kind, prec, m, column bucket) -> shape.  A shape is
 // tuned on one n and serves the n of its bucket: every n up to 16, then runs of
 // 8 up to 64, then of 32.
@@ -336,22 +336,7 @@ struct KernelTimer {
     }
 };
 
-// ---------------------------------------------------------------- colex blocks
-// Number of colex blocks of the prefixes of m-2 columns out of the first n-2
-// (the kernels' colex_block): per last column v, C(v, m-3) prefixes in runs of
-// colex_run(n-1-v, K).
-static unsigned long long colex_block_count(int m, int n, unsigned K) {
-    const int P = m - 2;
-    unsigned long long total = 0;
-    for (int v = P - 1; v <= n - 3; ++v) {
-        unsigned long long cnt = 0;
-        host_binomial(v, P - 1, &cnt);
-        const unsigned long long k = (unsigned long long)colex_run(n - 1 - v, K);
-        total += (cnt + k - 1) / k;
-    }
-    return total;
-}
-
+// ---------------------------------------------------------------- two-sided blocks
 // Number of two-sided blocks (the kernels' split_block): per last column v and
 // side s, split_count prefixes in runs of colex_run(n-1-v, K).
 static unsigned long long split_block_count(int m, int n, unsigned K) {
@@ -851,7 +836,7 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
         unsigned long long n_prefix = 0;
         host_binomial(n - 2, m - 2, &n_prefix);
         const unsigned K = 64u * (unsigned)(sh.spl_set ? sh.spl : kSharedSplInt);
-        const unsigned long long blocks = colex_block_count(m, n, K);
+        const unsigned long long blocks = split_block_count(m, n, K);
         const unsigned long long wpb = (unsigned long long)(block / kWave);
         unsigned long long g = (blocks + wpb - 1) / wpb;
         grid = (int)(g > (unsigned long long)kMaxGrid ? kMaxGrid : (g < 1 ? 1 : g));

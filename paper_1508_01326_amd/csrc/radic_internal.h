@@ -16,13 +16,13 @@ constexpr int kMaxBlock = 256;       // __launch_bounds__ of every enumeration k
 constexpr int kMaxGrid = 8192;       // partial-sum slots (one per workgroup) for single-matrix launches
 constexpr int kPrefixBlock = 64;     // prefixes of m-2 columns per wave block (prefix-shared kernels)
 constexpr int kGroupBlock = 16;      // prefixes of m-3 columns per wave block (group-shared kernel)
-// Colex blocks of a whole rank space (prefix-shared kernels): about this many
-// minors per block, so that the heaviest prefixes do not make one block the
-// whole launch's critical path.
+// Blocks of a whole rank space (prefix-shared kernels, see split_shape): about
+// this many minors per block, so that the heaviest prefixes do not make one
+// block the whole launch's critical path.
 constexpr unsigned kColexPairs = 2048;
 
-// Prefixes per colex block for prefixes with r later columns (C(r, 2) minors
-// each): about K minors, between 1 and kPrefixBlock prefixes.
+// Prefixes per block for prefixes with r later columns (C(r, 2) minors each):
+// about K minors, between 1 and kPrefixBlock prefixes.
 __host__ __device__ inline int colex_run(int r, unsigned K) {
     const unsigned pairs = (unsigned)(r * (r - 1) / 2);
     const unsigned k = pairs ? K / pairs : (unsigned)kPrefixBlock;

@@ -127,26 +127,33 @@ __device__ __forceinline__ void int_left_steps(double (&L)[M][P], double (&u)[P]
 // per lane; while their later columns fit the cap projected-column slots);
 // n_prefix = C(n-2, m-2) numbers all prefixes.  incl holds 2 x 64 scans (pairs,
 // then projected columns).  bt[x*bstride + y] = C(x, y) for y < M.  Wave-uniform
-// control flow outside the lanes' own walks.  COLEX: next and pi1 are colex
-// prefix numbers (unrank_prefix_colex) and the whole rank space is summed, so
-// no pair is clipped and rbase, R0, R1 are not used.
+// control flow outside the lanes' own walks.  COLEX: next and pi1 number the
+// side-`side` prefixes with last column vlast of a two-sided block (see
+// split_block; side 1 reads the matrix with its columns reversed) and the
+// whole rank space is summed, so no pair is clipped and rbase, R0, R1 are not
+// used.
 template <int M, bool COLEX = false>
 __device__ void int_prefix_range(const double* cr, int n, const unsigned long long* bt, int bstride,
                                  unsigned long long next, unsigned long long pi1, unsigned long long n_prefix,
                                  unsigned long long rbase,
                                  unsigned long long R0, unsigned long long R1, double p, double pinv, int cap,
-                                 IntSlot* slot, unsigned* incl, double2* tv, int lane, double& acc) {
+                                 IntSlot* slot, unsigned* incl, double2* tv, int lane, double& acc, int side = 0,
+                                 int vlast = 0) {
     constexpr int P = M - 2;
     constexpr int ST = IntLayout<M>::st;
+    if (!COLEX) side = 0;
     while (next < pi1 && (COLEX || rbase < R1)) {
         // lane l takes prefix next + l if it starts before R1 and its later
         // columns still fit the projected-column slots (lane 0 always does)
         const unsigned long long pi = next + lane;
         const bool inb = pi < pi1;
         int c[P];
-        if (COLEX) unrank_prefix_colex<P>(inb ? pi : next, n, bt, bstride, c);
+        if (COLEX) split_unrank<P>(inb ? pi : next, n, side, vlast, bt, bstride, c);
         else unrank_prefix<P>(inb ? pi : next, n, n_prefix, bt, bstride, c);
         const int r = n - 1 - c[P - 1];
+        // from here on c holds the matrix's columns: side 1 reads column c as n-1-c
+#pragma unroll
+        for (int k = 0; k < P; ++k) c[k] = side ? n - 1 - c[k] : c[k];
         const unsigned cfull = inb ? (unsigned)(r * (r - 1) / 2) : 0u;
         const unsigned cscan = wave_scan_u32(cfull, lane);
         const unsigned long long base = rbase + (cscan - cfull);
@@ -236,9 +243,12 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
             double inv = tinv;
             if (lane > 0) inv = mulmod(inv, before, p, pinv);
             if (lane < kWave - 1) inv = mulmod(inv, after, p, pinv);
-            // sign: prefix row exchanges and the prefix's share of (-1)^(r+s);
-            // the pair (a, b) adds 2 (n - r + 1) + its offsets
-            int ps = M * (M + 1) / 2 + P;
+            // sign: prefix row exchanges and the prefix's share of (-1)^(r+s) in
+            // its side's coordinates (column sum of the parity of side * P(n-1)
+            // + sum c; on side 1 a term of the reversed matrix is
+            // (-1)^(m(m-1)/2 + m(n+1)) times the matrix's own); the pair (a, b)
+            // adds 2 (n - r + 1) + its offsets
+            int ps = M * (M + 1) / 2 + P + (side ? M * (M - 1) / 2 + M * (n + 1) + P * (n - 1) : 0);
 #pragma unroll
             for (int k = 0; k < P; ++k) ps += c[k];
             const bool sg = neg ^ ((ps & 1) != 0);
@@ -305,7 +315,8 @@ __device__ void int_prefix_range(const double* cr, int n, const unsigned long lo
                 }
                 if (act) {
                     // slot g holds column c_{m-3} + 1 + (g - start of s) = n - send + g
-                    const double* colp = cr + (n - (int)send + (int)g) * ST;
+                    // of its side (the matrix's n-1-(n-send+g) on side 1)
+                    const double* colp = cr + (side ? (int)send - (int)g - 1 : n - (int)send + (int)g) * ST;
                     double x[M];
 #pragma unroll
                     for (int i = 0; i < M; ++i) x[i] = colp[off[i]];
