@@ -36,9 +36,14 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # sources hash to the same value.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "efa2a19483b16846ed6ceab17ea929f1f0171fb1d3035cceb87ba7253f6cfa0d", "fp64": 406368, "fp32_bulk": 3052832}
+PROFILED_TRAFFIC = {"sources_sha256": "0d0455bf8c97d0e5c569972678022334ef0008289697dc41630ed0db895a4ef5", "fp64": 410438, "fp32_bulk": 2533225}
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
-PROFILED_FLOPS = {"fp64": {"fp32": 2450688, "fp64": 460292608}, "fp32_bulk": {"fp32": 350846464, "fp64": 203616576}}
+PROFILED_FLOPS = {"fp64": {"fp32": 1476992, "fp64": 251909632}, "fp32_bulk": {"fp32": 208400000, "fp64": 138810240}}
+# VALU wave instructions per launch (SQ_INSTS_VALU) on the same sources
+PROFILED_VALU = {"fp64": 13570755, "fp32_bulk": 19972537}
+# wave-instruction issue rate of the VALUs: 256 CU x 4 SIMD x 2.4 GHz, one
+# 64-lane instruction per SIMD every 4 clocks (16 lanes per clock)
+PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4
 
 
 def kernel_sources_sha256():
@@ -352,6 +357,21 @@ def rocprof_flops(form, enumeration, kernel_ms):
             "source": "rocprofv3 counters per launch (profiles/k_radic_shared_8x32.md)"}
 
 
+def valu_issue(form, enumeration, kernel_ms):
+    """VALU wave instructions per launch of the prefix-shared kernel from its
+    rocprofv3 counter (SQ_INSTS_VALU), over this run's kernel time, against the
+    chip's issue rate: the bound these kernels meet, since most of their
+    instructions are not floating point; None once the kernel sources differ
+    from those profiled."""
+    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+        return None
+    v = PROFILED_VALU[form]
+    rate = v / (kernel_ms * 1e-3)
+    return {"valu_instructions": v, "achieved": rate, "peak": PEAK_VALU_ISSUE, "unit": "wave instructions/s",
+            "frac": rate / PEAK_VALU_ISSUE,
+            "source": "rocprofv3 SQ_INSTS_VALU per launch (profiles/k_radic_shared_8x32.md)"}
+
+
 def kernel_name(enumeration, form):
     if enumeration == "per_minor":
         return "k_radic_float<8,true,false,true>" if form == "fp32_bulk" else "k_radic_float<8,false,false,false>"
@@ -550,6 +570,7 @@ def main():
                                                         f"FLOP per minor x {total} minors = {flop:.4g} FLOP, "
                                                         f"a different method's work"},
                      "rocprof_flops": rocprof_flops(dom, args.enumeration, dom_ms),
+                     "valu_issue": valu_issue(dom, args.enumeration, dom_ms),
                      "kernel_ms": dom_ms, "launches_timed": len(timed),
                      "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},
         "cpu_baseline": cpu,
