@@ -399,6 +399,24 @@ int radic_host_prime(int i, uint32_t *hPrime);
  * EINVAL for bad arguments, EOVERFLOW when C(n, m) >= 2^63. */
 int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uint64_t *hChunk,
                               uint64_t *hChunks);
+/* The blocks radic_det and radic_det_int_exact take a whole rank space in
+ * (3 <= m <= RADIC_MAX_M), computed on the host by the kernels' own code.  Each
+ * minor j_0 < ... < j_{m-1} (0-based) is grouped either with the minors that
+ * share its first m-2 columns (side 0, n-1-j_{m-3} columns after them) or with
+ * those that share its last m-2 (side 1, j_2 columns before them), whichever
+ * leaves more (side 0 on a tie); side 1 is side 0 of the column-reversed matrix
+ * (column c read as n-1-c).  A side's prefixes c_0 < ... < c_{m-3} (0-based, in
+ * that side's coordinates) are grouped by their last column v = c_{m-3},
+ * m-3 <= v <= n-3.
+ *   radic_host_split_count: *hCount prefixes of side `side` with last column v.
+ *   radic_host_split_prefix: the j-th of them (j < that count) into
+ *     hCols[0..m-3] (m-2 entries).
+ *   radic_host_split_blocks: *hBlocks blocks of about minors_per_block minors
+ *     (the launchers use 64 * subsets_per_lane).
+ * EINVAL for bad arguments, EOVERFLOW when C(n, m) >= 2^63. */
+int radic_host_split_count(int m, int n, int side, int v, uint64_t *hCount);
+int radic_host_split_prefix(int m, int n, int side, int v, uint64_t j, int *hCols);
+int radic_host_split_blocks(int m, int n, int minors_per_block, uint64_t *hBlocks);
 
 #ifdef __cplusplus
 }

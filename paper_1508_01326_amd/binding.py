@@ -89,6 +89,9 @@ SIGNATURES = {
     "radic_host_unrank": (_i, [_i, _i, _u64, _ip]),
     "radic_host_prime": (_i, [_i, _u32p]),
     "radic_host_batch_chunking": (_i, [_i, _i, _i, _i, _u64p, _u64p]),
+    "radic_host_split_count": (_i, [_i, _i, _i, _i, _u64p]),
+    "radic_host_split_prefix": (_i, [_i, _i, _i, _i, _u64, _ip]),
+    "radic_host_split_blocks": (_i, [_i, _i, _i, _u64p]),
     "radic_set_prime_set": (_i, [_u32p, _i]),
 }
 
@@ -369,6 +372,28 @@ def host_batch_chunking(dtype, m, n, subsets_per_lane):
     _check(lib().radic_host_batch_chunking(int(dtype), int(m), int(n), int(subsets_per_lane), ctypes.byref(c),
                                            ctypes.byref(k)), "radic_host_batch_chunking")
     return int(c.value), int(k.value)
+
+
+def host_split_count(m, n, side, v):
+    """Prefixes of one side of the two-sided blocks with last column v."""
+    c = ctypes.c_uint64(0)
+    _check(lib().radic_host_split_count(int(m), int(n), int(side), int(v), ctypes.byref(c)), "radic_host_split_count")
+    return int(c.value)
+
+
+def host_split_prefix(m, n, side, v, j):
+    """The j-th such prefix: m-2 columns, 0-based, in that side's coordinates."""
+    cols = (ctypes.c_int * (m - 2))()
+    _check(lib().radic_host_split_prefix(int(m), int(n), int(side), int(v), int(j), cols), "radic_host_split_prefix")
+    return list(cols)
+
+
+def host_split_blocks(m, n, minors_per_block):
+    """Blocks a whole rank space is taken in, about minors_per_block minors each."""
+    c = ctypes.c_uint64(0)
+    _check(lib().radic_host_split_blocks(int(m), int(n), int(minors_per_block), ctypes.byref(c)),
+           "radic_host_split_blocks")
+    return int(c.value)
 
 
 # ------------------------------------------------------------------ batched

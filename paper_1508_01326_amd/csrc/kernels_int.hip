@@ -90,6 +90,8 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int(IntJob J) {
     const int waves = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
+    // primes beyond the bound kernel's count have nothing to do (see above)
+    if ((int)blockIdx.y >= J.header->n_primes || J.header->status != RADIC_OK) return;
     const double p = g_prime[blockIdx.y];
     const double pinv = g_prime_inv[blockIdx.y];
 
@@ -166,6 +168,7 @@ struct IntSharedJob {
     int grid_x;
     unsigned long long q_begin, count, total, n_prefix, p_begin, p_end;
     double* partials;             // [prime][grid_x] residues
+    const IntHeader* header;      // the bound kernel's prime count and status
     int colex;                    // 1: two-sided blocks of the whole rank space (see split_block)
     unsigned colex_pairs;
     unsigned long long colex_blocks;
@@ -183,6 +186,9 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
     __shared__ double red[16];
     const int n = J.n;
     const int waves = blockDim.x / kWave, wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    // the launch covers an upper bound on the primes: those the bound kernel
+    // did not ask for (or every one, when it failed) have nothing to do
+    if ((int)blockIdx.y >= J.header->n_primes || J.header->status != RADIC_OK) return;
     const double p = g_prime[blockIdx.y];
     const double pinv = g_prime_inv[blockIdx.y];
 
@@ -243,11 +249,13 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
 // 64-bit integer sums are exact), then Garner's algorithm (mixed radix digits
 // v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
 // representative in (-P/2, P/2] as sign and 32-bit limbs.
-__global__ __launch_bounds__(256) void k_int_finalize(const double* partials, int grid_x, const IntHeader* h,
-                                                      IntResult* out) {
+// `launched`: the primes the modular kernel was launched for (an upper bound on
+// the bound kernel's count; a larger count would leave residues missing).
+__global__ __launch_bounds__(256) void k_int_finalize(const double* partials, int grid_x, int launched,
+                                                      const IntHeader* h, IntResult* out) {
     __shared__ unsigned long long res[RADIC_MAX_PRIMES];
     __shared__ unsigned long long red[256 / kWave];
-    const int k = h->n_primes;
+    const int k = h->n_primes <= launched ? h->n_primes : 0;
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, waves = blockDim.x / kWave;
     for (int t = 0; t < k; ++t) {
         unsigned long long s = 0;
@@ -265,8 +273,8 @@ __global__ __launch_bounds__(256) void k_int_finalize(const double* partials, in
     if (threadIdx.x != 0) return;
     IntResult r{};
     r.n_primes = k;
-    r.status = h->status;
-    if (h->status != RADIC_OK) {
+    r.status = h->n_primes <= launched ? h->status : RADIC_EDEVICE;
+    if (r.status != RADIC_OK) {
         *out = r;
         return;
     }
@@ -362,6 +370,7 @@ hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned
     J.colex_pairs = colex_pairs;
     J.colex_blocks = colex_blocks;
     J.partials = reinterpret_cast<double*>(static_cast<unsigned char*>(ws) + int_partials_offset());
+    J.header = reinterpret_cast<const IntHeader*>(ws);
     const int lds = int_shared_lds(m, n, block / kWave, cap);
     switch (m) {
 #define RADIC_CASE(MM) \
@@ -373,11 +382,11 @@ hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned
     }
 }
 
-hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s) {
+hipError_t launch_int_finalize(int grid_x, int launched, void* ws, hipStream_t s) {
     unsigned char* w = static_cast<unsigned char*>(ws);
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_int_finalize, dim3(1), dim3(256), 0, s,
-                       reinterpret_cast<const double*>(w + int_partials_offset()), grid_x,
+                       reinterpret_cast<const double*>(w + int_partials_offset()), grid_x, launched,
                        reinterpret_cast<const IntHeader*>(w), reinterpret_cast<IntResult*>(w + int_result_offset()));
     return hipGetLastError();
 }

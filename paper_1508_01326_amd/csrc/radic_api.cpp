@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "radic_internal.h"
+#include "split.h"
 
 namespace radic {
 
@@ -32,7 +33,7 @@ hipError_t upload_primes(const unsigned* primes, int count);
 hipError_t launch_int_bound(const int* A, int m, int n, long long lda, void* ws, int prime_count, hipStream_t s);
 hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned long long count, int spl,
                            int grid_x, int n_primes, int block, void* ws, hipStream_t s);
-hipError_t launch_int_finalize(int grid_x, void* ws, hipStream_t s);
+hipError_t launch_int_finalize(int grid_x, int launched, void* ws, hipStream_t s);
 int int_shared_lds(int m, int n, int waves, int cap);
 size_t run_bytes();
 hipError_t launch_2xn(const double* A, long long lda, long long n, int G, void* runs, void* flag,
@@ -689,6 +690,69 @@ static float time_runs(F fn, hipStream_t stream, int reps, int* rc_out) {
 
 }  // namespace
 
+// Two-sided blocks on the host: the kernels' own enumeration (split.h) over a
+// host binomial table C(x, y), x <= n, y <= m (0 where it does not fit 64 bits,
+// never read then: the space is below kRankLimit).
+static std::vector<unsigned long long> host_binom_table(int n, int m) {
+    std::vector<unsigned long long> t((size_t)(n + 1) * (m + 1), 0ull);
+    for (int x = 0; x <= n; ++x)
+        for (int y = 0; y <= m; ++y) {
+            unsigned long long v = 0;
+            if (host_binomial(x, y, &v) == RADIC_OK) t[(size_t)x * (m + 1) + y] = v;
+        }
+    return t;
+}
+
+static int split_args(int m, int n, int side, int v) {
+    if (m < 3 || m > RADIC_MAX_M || n < m || n > RADIC_MAX_N || side < 0 || side > 1 || v < m - 3 || v > n - 3)
+        return RADIC_EINVAL;
+    unsigned long long total = 0;
+    if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
+    return RADIC_OK;
+}
+
+template <int P>
+static void host_split_p(int n, int side, int v, unsigned long long j, const unsigned long long* bt, int stride,
+                         unsigned long long* count, int* cols) {
+    if (count) *count = split_count<P>(n, side, v, bt, stride);
+    if (cols) {
+        int c[P];
+        split_unrank<P>(j, n, side, v, bt, stride, c);
+        for (int k = 0; k < P; ++k) cols[k] = c[k];
+    }
+}
+
+static void host_split(int m, int n, int side, int v, unsigned long long j, unsigned long long* count, int* cols) {
+    const std::vector<unsigned long long> bt = host_binom_table(n, m);
+    const unsigned long long* b = bt.data();
+    const int st = m + 1;
+    switch (m - 2) {
+#define RADIC_CASE(PP) \
+    case PP: host_split_p<PP>(n, side, v, j, b, st, count, cols); break;
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10)
+#undef RADIC_CASE
+        default: break;
+    }
+}
+
+// Primes the exact path's modular kernel is launched for, enough for any int32
+// matrix of the shape.  The bound kernel asks for the fewest primes whose
+// product exceeds 2 (e_m + 1), e_m the m-th elementary symmetric function of
+// the column norms (at least sum |det(A_J)| by Hadamard's inequality).  Entries
+// below 2^31 in magnitude give column norms below sqrt(m) 2^31, so
+// e_m < C(n, m) (sqrt(m) 2^31)^m; the same rule on that bound, with a bit of
+// margin, plus one prime, never asks for fewer.
+static int int_prime_upper_bound(int m, int n, const std::vector<unsigned>& primes) {
+    unsigned long long c = 0;
+    host_binomial(n, m, &c);
+    const double need = std::log2((double)c) + m * (31.0 + 0.5 * std::log2((double)m)) + 2.01;
+    double have = 0.0;
+    int k = 0;
+    while (k < (int)primes.size() && have <= need) have += std::log2((double)primes[k++]);
+    return std::min((int)primes.size(), k + 1);
+}
+
 extern "C" {
 
 const char* radic_status_string(int status) {
@@ -802,22 +866,21 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     int rc = check_workspace(dWork, work_bytes, int_workspace_bytes());
     if (rc != RADIC_OK) return rc;
     if ((rc = ensure_device()) != RADIC_OK) return rc;
-    int prime_count;
+    std::vector<unsigned> primes;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        prime_count = (int)g_primes.size();
+        primes = g_primes;
     }
+    const int prime_count = (int)primes.size();
     Shape sh = pick_shape(RADIC_WS_INT, 0, m, n);
     if (int_lds(m, n) > kMaxLds) return RADIC_ENOTSUP;
-    // 1. bound -> number of primes (read back: this entry point is synchronous)
+    // 1. bound -> number of primes, on the device; the modular kernel is
+    // launched for an upper bound on it that needs no look at A (entries below
+    // 2^31 in magnitude), and the primes it does not need exit at once, so the
+    // only host synchronisation is the final read-back
     hipError_t e = launch_int_bound(dA, m, n, lda, dWork, prime_count, stream);
     if (e != hipSuccess) return device_error("launch of the bound kernel", e);
-    int hdr[2] = {0, 0};
-    e = hipMemcpyAsync(hdr, dWork, sizeof(hdr), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return device_error("read-back of the prime count", e);
-    if (hdr[1] != RADIC_OK) return RADIC_EOVERFLOW;
-    const int k = hdr[0];
+    const int k = int_prime_upper_bound(m, n, primes);
     // 2. residue sums per (workgroup, prime), 3. CRT
     int mode;
     {
@@ -849,7 +912,7 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
         e = launch_int_main(dA, m, n, lda, total, sh.spl, grid, k, sh.block, dWork, stream);
     }
     if (e != hipSuccess) return device_error("launch of the modular kernel", e);
-    e = launch_int_finalize(grid, dWork, stream);
+    e = launch_int_finalize(grid, k, dWork, stream);
     if (e != hipSuccess) return device_error("launch of the CRT kernel", e);
     std::vector<unsigned char> res(int_result_size());
     e = hipMemcpyAsync(res.data(), static_cast<unsigned char*>(dWork) + int_result_offset(), res.size(),
@@ -1323,6 +1386,35 @@ int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uin
     host_batch_chunking(dtype, total, subsets_per_lane, &c, &k);
     *hChunk = c;
     *hChunks = k;
+    return RADIC_OK;
+}
+
+int radic_host_split_count(int m, int n, int side, int v, uint64_t* hCount) {
+    if (!hCount) return RADIC_EINVAL;
+    const int rc = split_args(m, n, side, v);
+    if (rc != RADIC_OK) return rc;
+    unsigned long long c = 0;
+    host_split(m, n, side, v, 0, &c, nullptr);
+    *hCount = c;
+    return RADIC_OK;
+}
+
+int radic_host_split_prefix(int m, int n, int side, int v, uint64_t j, int* hCols) {
+    if (!hCols) return RADIC_EINVAL;
+    const int rc = split_args(m, n, side, v);
+    if (rc != RADIC_OK) return rc;
+    unsigned long long c = 0;
+    host_split(m, n, side, v, 0, &c, nullptr);
+    if (j >= c) return RADIC_EINVAL;
+    host_split(m, n, side, v, j, nullptr, hCols);
+    return RADIC_OK;
+}
+
+int radic_host_split_blocks(int m, int n, int minors_per_block, uint64_t* hBlocks) {
+    if (!hBlocks || minors_per_block < 1) return RADIC_EINVAL;
+    const int rc = split_args(m, n, 0, m - 3);
+    if (rc != RADIC_OK) return rc;
+    *hBlocks = split_block_count(m, n, (unsigned)minors_per_block);
     return RADIC_OK;
 }
 

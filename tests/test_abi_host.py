@@ -223,3 +223,59 @@ def test_batch_chunking_bounds():
         radic.host_batch_chunking(2, 3, 5, 1)
     with pytest.raises(radic.RadicError):
         radic.host_batch_chunking(0, 6, 5, 1)
+
+
+def _colex_run(r, K):
+    pairs = r * (r - 1) // 2
+    k = K // pairs if pairs else 64
+    return max(1, min(64, k))
+
+
+@pytest.mark.parametrize("m,n", [(3, 9), (4, 11), (5, 5), (5, 12), (6, 7), (6, 20), (7, 18), (8, 16), (9, 17),
+                                 (10, 17), (11, 16), (12, 17)])
+def test_split_blocks_partition(m, n):
+    # the kernels' two-sided enumeration, run on the host: every minor lies on
+    # exactly one side, under exactly one prefix of it, and a side-s prefix c
+    # with last column v is taken exactly when c_2 <= n-1-v-s (m >= 5); side 1
+    # reads column c as n-1-c
+    seen = set()
+    blocks = 0
+    K = 64 * 64
+    for v in range(m - 3, n - 2):
+        r = n - 1 - v
+        for side in (0, 1):
+            cnt = radic.host_split_count(m, n, side, v)
+            if m < 5 and side == 1:
+                assert cnt == 0
+            blocks += -(-cnt // _colex_run(r, K))
+            for j in range(cnt):
+                c = radic.host_split_prefix(m, n, side, v, j)
+                assert c == sorted(set(c)) and c[-1] == v and c[0] >= 0
+                if m >= 5:
+                    assert c[2] <= r - side
+                for a in range(v + 1, n):
+                    for b in range(a + 1, n):
+                        view = c + [a, b]
+                        minor = tuple(sorted(n - 1 - x for x in view)) if side else tuple(view)
+                        assert minor not in seen
+                        seen.add(minor)
+            with pytest.raises(radic.RadicError):
+                radic.host_split_prefix(m, n, side, v, cnt)
+    assert len(seen) == math.comb(n, m)
+    assert radic.host_split_blocks(m, n, K) == blocks
+
+
+def test_split_counts_match_the_bench_model():
+    # two independent statements of the side rule: the kernels' (C++, host
+    # build) and the executed-FLOP model of bench.py
+    import bench
+    for m, n in [(5, 14), (6, 40), (8, 32), (9, 30), (12, 36), (10, 64)]:
+        for v in range(m - 3, n - 2):
+            for side in (0, 1):
+                assert radic.host_split_count(m, n, side, v) == bench.split_prefix_count(m - 2, n, side, v)
+    with pytest.raises(radic.RadicError):
+        radic.host_split_count(2, 5, 0, 0)
+    with pytest.raises(radic.RadicError):
+        radic.host_split_count(5, 9, 2, 3)
+    with pytest.raises(radic.RadicError):
+        radic.host_split_count(5, 9, 0, 7)
