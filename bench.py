@@ -34,7 +34,7 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # summary and commands are in profiles/k_radic_shared_8x32.md).  They hold for
 # the kernel sources they were taken on: `traffic` is reported only while the
 # sources hash to the same value.
-KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "stage.h", "lu_float.h", "enumerate.h",
+KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "split.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
 PROFILED_TRAFFIC = {"sources_sha256": "0d0455bf8c97d0e5c569972678022334ef0008289697dc41630ed0db895a4ef5", "fp64": 410438, "fp32_bulk": 2533225}
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources

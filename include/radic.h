@@ -393,10 +393,14 @@ int radic_host_unrank(int m, int n, uint64_t q, int *hCols);
 int radic_host_prime(int i, uint32_t *hPrime);
 /* How radic_det_batched cuts the rank space of one matrix (dtype 0 float64,
  * 1 int32) into chunks, the unit a wave takes from its class queue (the
- * granularity scheme of Section 5): *hChunk ranks per chunk (a multiple of 64,
- * at least 64 * subsets_per_lane), *hChunks chunks.  Float matrices have at
- * most 256 chunks (one partial-sum slot each), int32 matrices at most 2^16.
- * EINVAL for bad arguments, EOVERFLOW when C(n, m) >= 2^63. */
+ * granularity scheme of Section 5).  Float matrices with m >= 3 and int32
+ * matrices with 3 <= m <= 6 are taken in the two-sided blocks of radic_det
+ * (radic_host_split_blocks with 64 * subsets_per_lane minors per block):
+ * *hChunk blocks per chunk.  The others are cut into rank windows: *hChunk
+ * ranks per chunk (a multiple of 64, at least 64 * subsets_per_lane).
+ * *hChunks chunks; float matrices have at most 256 (one partial-sum slot
+ * each), int32 matrices at most 2^16.  EINVAL for bad arguments, EOVERFLOW
+ * when C(n, m) >= 2^63. */
 int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uint64_t *hChunk,
                               uint64_t *hChunks);
 /* The blocks radic_det and radic_det_int_exact take a whole rank space in

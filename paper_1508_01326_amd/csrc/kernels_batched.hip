@@ -32,8 +32,9 @@ constexpr int kBatchWaves = 4;           // waves per workgroup of the persisten
 
 struct BatchMeta {
     unsigned long long total;    // C(n, m)
-    unsigned long long chunk;    // ranks per chunk (a multiple of 64)
+    unsigned long long chunk;    // ranks per chunk (a multiple of 64), or blocks per chunk (blocks > 0)
     unsigned long long nchunks;
+    unsigned long long blocks;   // two-sided blocks of the matrix (batch_uses_blocks), else 0
     int status;                  // per-matrix radic status
     int kind;                    // 0 float, 1 exact, -1 no work (error or m > n)
     int n_primes;
@@ -106,6 +107,45 @@ __host__ __device__ inline size_t batch_ws_bytes(int batch) {
     return off_residues(batch) + align256(8 * (size_t)RADIC_MAX_PRIMES * batch);
 }
 
+// Two-sided blocks of about K minors of an m x n matrix (the single-matrix
+// kernels' split_block order), counted by the wave: lanes take (v, side) pairs.
+template <int P>
+__device__ unsigned long long split_blocks_wave_p(int n, unsigned K, int lane) {
+    unsigned long long nb = 0;
+    for (int v0 = P - 1; v0 <= n - 3; v0 += kWave / 2) {
+        const int v = v0 + lane / 2;
+        if (v <= n - 3) nb += split_blocks_at<P>(n, lane & 1, v, K, g_binom, kBinomCols);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) nb += __shfl_xor(nb, o, kWave);
+    return nb;
+}
+
+__device__ unsigned long long split_blocks_wave(int m, int n, unsigned K, int lane) {
+    switch (m - 2) {
+#define RADIC_CASE(PP) \
+    case PP: return split_blocks_wave_p<PP>(n, K, lane);
+        RADIC_CASE(1) RADIC_CASE(2) RADIC_CASE(3) RADIC_CASE(4) RADIC_CASE(5) RADIC_CASE(6)
+        RADIC_CASE(7) RADIC_CASE(8) RADIC_CASE(9) RADIC_CASE(10)
+#undef RADIC_CASE
+        default: return 0ull;
+    }
+}
+
+// Chunking of one matrix: runs of two-sided blocks (batch_uses_blocks), else
+// rank windows (batch_chunking).
+__device__ void chunk_matrix(int kind, int m, int n, unsigned long long total, int spl, int lane, BatchMeta& mt) {
+    if (batch_uses_blocks(kind, m)) {
+        const unsigned K = 64u * (unsigned)(spl > 0 ? spl : 1);
+        mt.blocks = split_blocks_wave(m, n, K, lane);
+        batch_block_chunking(mt.blocks, kind == 0 ? (unsigned long long)kBatchChunksPerMatrix : kExactChunksMax,
+                             mt.chunk, mt.nchunks);
+    } else {
+        mt.blocks = 0;
+        batch_chunking(kind, total, spl, mt.chunk, mt.nchunks);
+    }
+}
+
 // ---------------------------------------------------------------- setup
 // One wave per matrix: its lanes read the matrix together (lane j column j, for
 // j < n), and the wave reduces what the matrix's meta needs.
@@ -134,7 +174,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
         } else if (d.dtype == 0) {
             mt.kind = 0;
             mt.total = total;
-            batch_chunking(0, total, J.spl_float, mt.chunk, mt.nchunks);
+            chunk_matrix(0, d.m, d.n, total, J.spl_float, lane, mt);
             const double* A = J.f64 + d.offset;
             int se = 0;
             bool bad = false;
@@ -186,7 +226,7 @@ __global__ __launch_bounds__(256) void k_batch_setup(BatchJob J) {
                 mt.kind = 1;
                 mt.total = total;
                 mt.n_primes = k;
-                batch_chunking(1, total, J.spl_int, mt.chunk, mt.nchunks);
+                chunk_matrix(1, d.m, d.n, total, J.spl_int, lane, mt);
             }
         }
     }
@@ -368,9 +408,10 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
 }
 
 // ---------------------------------------------------------------- float chunks, prefix-shared (m >= 3)
-// From m = 3 a float chunk runs the prefix-shared round of the single-matrix
-// kernels over its rank window: the minors of a prefix (first m-2 columns)
-// share its elimination steps and end with a 2 x 2 determinant.  FP32-bulk
+// From m = 3 a float chunk is a run of the matrix's two-sided blocks (as the
+// single-matrix kernels take a whole rank space, see split_shape), each worked
+// by the prefix-shared round: the minors of a prefix (first m-2 columns of its
+// side) share its elimination steps and end with a 2 x 2 determinant.  FP32-bulk
 // queues its flagged minors in the wave's LDS and refactors them in double by
 // lane groups (between rounds once the queue is half full, and at the end of
 // the chunk); a round whose flagged minors would not fit is done again in
@@ -433,16 +474,19 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     constexpr int S64 = SharedLayout<M>::s64;
     if (restage) stage_float_shared<M, F32>(J, d, L, lane);
     const int n = d.n;
-    const unsigned long long R0 = c * mt.chunk;
-    const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
-    // the chunk as a rank window of the single-matrix round
+    // the chunk is the run [b0, b1) of the matrix's two-sided blocks, each
+    // taken as by the single-matrix kernel (its whole rank space, no clipping)
+    const unsigned K = 64u * (unsigned)(J.spl_float > 0 ? J.spl_float : 1);
+    const unsigned long long b0 = c * mt.chunk;
+    const unsigned long long b1 = b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks;
     FloatJob FJ{};
     FJ.n = n;
-    FJ.q_begin = R0;
-    FJ.count = R1 - R0;
+    FJ.q_begin = 0;
+    FJ.count = mt.total;
     FJ.total = mt.total;
     FJ.tau = J.tau;
-    FJ.colex = 0;
+    FJ.colex = 1;
+    FJ.colex_pairs = K;
     FJ.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
     FJ.cap = kBatchSharedCap;
     FJ.defer_cap = kBatchDefer;
@@ -454,55 +498,60 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     W.ratios = reinterpret_cast<float*>(L.rec + kHdrBytes + kScanBytes);
     W.wcols = reinterpret_cast<uint4*>(L.rec + kHdrBytes + kScanBytes + kPrefixBlock * 4);
     W.tv = reinterpret_cast<unsigned char*>(L.tv);
-    // the prefixes holding the window's first and last ranks
-    unsigned long long next = prefix_of_rank<M>(R0, n, bt, kBatchBS);
-    const unsigned long long pi1 = prefix_of_rank<M>(R1 - 1, n, bt, kBatchBS) + 1;
     double hi = 0.0, lo = 0.0, ab = 0.0;
     unsigned long long nfb = 0;
     int gcount = 0;
     unsigned minors;
-    if constexpr (F32) {
-        if (!mt.all_double) {
-            while (next < pi1) {
-                const double shi = hi, slo = lo, sab = ab;
-                const unsigned long long snfb = nfb;
-                const int sg = gcount;
-                const int ntake = shared_round<M, true, kBatchBS>(FJ, bt, L.cf, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab,
-                                                                  nfb, gcount, minors);
-                if (gcount > FJ.defer_cap) {
-                    // the round's flagged minors do not fit the queue: the round
-                    // again, in double (every one of its minors counted as refactored)
-                    hi = shi;
-                    lo = slo;
-                    ab = sab;
-                    nfb = snfb;
-                    gcount = sg;
+    const bool f32 = F32 && !mt.all_double;
+    for (unsigned long long blk = b0; blk < b1; ++blk) {
+        unsigned long long next;
+        int cnt, side, vlast;
+        split_block<M - 2>(blk, n, bt, kBatchBS, K, lane, side, vlast, next, cnt);
+        const unsigned long long pi1 = next + (unsigned long long)cnt;
+        if constexpr (F32) {
+            if (f32) {
+                while (next < pi1) {
+                    const double shi = hi, slo = lo, sab = ab;
+                    const unsigned long long snfb = nfb;
+                    const int sg = gcount;
+                    const int ntake = shared_round<M, true, kBatchBS>(FJ, bt, L.cf, next, pi1, side, vlast, W, lane,
+                                                                      0ull, hi, lo, ab, nfb, gcount, minors);
+                    if (gcount > FJ.defer_cap) {
+                        // the round's flagged minors do not fit the queue: the
+                        // round again, in double (every one of its minors counted
+                        // as refactored)
+                        hi = shi;
+                        lo = slo;
+                        ab = sab;
+                        nfb = snfb;
+                        gcount = sg;
+                        wave_lds_sync();
+                        (void)shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, side, vlast, W, lane, 0ull, hi,
+                                                               lo, ab, nfb, gcount, minors);
+                        if (lane == 0) nfb += minors;
+                    }
+                    next += (unsigned long long)ntake;
                     wave_lds_sync();
-                    (void)shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab, nfb,
-                                                           gcount, minors);
-                    if (lane == 0) nfb += minors;
+                    relieve_segment<M, S64>(FJ, L.cd, 0ull, gcount, lane, hi, lo, ab);
                 }
-                next += (unsigned long long)ntake;
-                wave_lds_sync();
-                relieve_segment<M, S64>(FJ, L.cd, 0ull, gcount, lane, hi, lo, ab);
+                continue;
             }
-            if (gcount > 0) {
-                __threadfence_block();   // the entries other lanes of the wave stored
-                refactor_queue_groups<M, S64>(L.cd, L.queue, gcount, lane, hi, lo, ab);
-            }
-            wave_reduce_partial(hi, lo, ab, nfb);
-            out = Partial{hi, lo, ab, nfb};
-            return;
+        }
+        // double rounds (FP64, or FP32-bulk under kF32MinMinors minors: every
+        // minor counted as done in double)
+        while (next < pi1) {
+            const int ntake = shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, side, vlast, W, lane, 0ull, hi,
+                                                               lo, ab, nfb, gcount, minors);
+            if (F32 && lane == 0) nfb += minors;
+            next += (unsigned long long)ntake;
+            wave_lds_sync();
         }
     }
-    // double rounds (FP64, or FP32-bulk under kF32MinMinors minors: every minor
-    // counted as done in double)
-    while (next < pi1) {
-        const int ntake = shared_round<M, false, kBatchBS>(FJ, bt, L.cd, next, pi1, 0, 0, W, lane, 0ull, hi, lo, ab, nfb,
-                                                           gcount, minors);
-        if (F32 && lane == 0) nfb += minors;
-        next += (unsigned long long)ntake;
-        wave_lds_sync();
+    if constexpr (F32) {
+        if (gcount > 0) {
+            __threadfence_block();   // the entries other lanes of the wave stored
+            refactor_queue_groups<M, S64>(L.cd, L.queue, gcount, lane, hi, lo, ab);
+        }
     }
     wave_reduce_partial(hi, lo, ab, nfb);
     out = Partial{hi, lo, ab, nfb};
@@ -550,9 +599,9 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
 
 // ---------------------------------------------------------------- exact chunks
 // Exact chunks share elimination steps: the minors of a prefix (first m-2
-// columns) for 3 <= m < kGroupExactMin, of a group (first m-3 columns) from
-// there to m = 10 (groups hold C(r, 3) minors against C(r, 2) per prefix).
-constexpr int kGroupExactMin = 7;
+// columns, two-sided blocks) for 3 <= m < kGroupExactMin, of a group (first m-3
+// columns, rank windows) from there to m = 10 (groups hold C(r, 3) minors
+// against C(r, 2) per prefix).
 // projected-column slots (16 bytes) per wave: enough for 64 prefixes or groups
 // of the narrow matrices a batch holds
 template <int M> constexpr int batch_cap() { return M >= kGroupExactMin ? 512 : 256; }
@@ -600,15 +649,13 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
         }
         return;
     } else if constexpr (M >= 3 && M <= 10) {
-        // prefix-shared: the chunk's ranks [R0, R1), prefixes from the one holding R0
-        const unsigned long long R0 = c * mt.chunk;
-        const unsigned long long R1 = R0 + mt.chunk < mt.total ? R0 + mt.chunk : mt.total;
-        PrefixSpace sp;
-        sp.n = n;
-        sp.total = mt.total;
-        sp.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
-        const unsigned long long first = prefix_of_rank<M>(R0, n, bt, RADIC_MAX_M);
-        const unsigned long long rbase = first_completion_rank<M>(first, sp, bt, RADIC_MAX_M);
+        // prefix-shared: the chunk is the run [b0, b1) of the matrix's
+        // two-sided blocks, each its whole rank space's as in the single-matrix
+        // kernel
+        const unsigned K = 64u * (unsigned)(J.spl_int > 0 ? J.spl_int : 1);
+        const unsigned long long b0 = c * mt.chunk;
+        const unsigned long long b1 = b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks;
+        const unsigned long long n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
         for (int pi = 0; pi < mt.n_primes; ++pi) {
             const double p = g_prime[pi], pinv = g_prime_inv[pi];
             wave_lds_sync();
@@ -620,8 +667,14 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
             }
             wave_lds_sync();
             double acc = 0.0;
-            int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, R0, R1, p, pinv, batch_cap<M>(),
-                                L.slot, L.incl, L.tv, lane, acc);
+            for (unsigned long long blk = b0; blk < b1; ++blk) {
+                unsigned long long next;
+                int cnt, side, vlast;
+                split_block<M - 2>(blk, n, bt, RADIC_MAX_M, K, lane, side, vlast, next, cnt);
+                int_prefix_range<M, true>(L.cr, n, bt, RADIC_MAX_M, next, next + (unsigned long long)cnt, n_prefix,
+                                          0ull, 0ull, mt.total, p, pinv, batch_cap<M>(), L.slot, L.incl, L.tv, lane,
+                                          acc, side, vlast);
+            }
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);
             if (lane == 0) atomicAdd(&J.residues[(size_t)b * RADIC_MAX_PRIMES + pi], (unsigned long long)acc);

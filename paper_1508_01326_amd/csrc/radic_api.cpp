@@ -1383,7 +1383,12 @@ int radic_host_batch_chunking(int dtype, int m, int n, int subsets_per_lane, uin
     unsigned long long total = 0;
     if (host_binomial(n, m, &total) != RADIC_OK || total >= kRankLimit) return RADIC_EOVERFLOW;
     unsigned long long c = 0, k = 0;
-    host_batch_chunking(dtype, total, subsets_per_lane, &c, &k);
+    if (batch_uses_blocks(dtype, m)) {
+        const unsigned long long nb = split_block_count(m, n, 64u * (unsigned)subsets_per_lane);
+        batch_block_chunking(nb, dtype == 0 ? (unsigned long long)kBatchChunksPerMatrix : (1ull << 16), c, k);
+    } else {
+        host_batch_chunking(dtype, total, subsets_per_lane, &c, &k);
+    }
     *hChunk = c;
     *hChunks = k;
     return RADIC_OK;

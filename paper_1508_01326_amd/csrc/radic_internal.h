@@ -60,6 +60,23 @@ __host__ __device__ inline void split_shape(int P, int n, int side, int v, int& 
 __host__ __device__ constexpr bool shared_tail_refactor(int m) { return m <= 8; }
 constexpr int kFallbackCap = 128;    // per-wave queue of minors awaiting an FP64 refactorisation
 constexpr int kBatchChunksPerMatrix = 256;
+// Batched exact chunks share the first m-3 elimination steps per group (3 x 3
+// determinant per minor) from this m on, up to m = 10.
+constexpr int kGroupExactMin = 7;
+// Batched matrices whose chunks are runs of the two-sided blocks of the
+// single-matrix kernels (float m >= 3, exact 3 <= m < kGroupExactMin); the
+// others are cut into rank windows.
+__host__ __device__ inline bool batch_uses_blocks(int kind, int m) {
+    return kind == 0 ? m >= 3 : (m >= 3 && m < kGroupExactMin);
+}
+// Chunks of a matrix taken in two-sided blocks: runs of chunk blocks, at most
+// most_chunks of them.
+__host__ __device__ inline void batch_block_chunking(unsigned long long nblocks, unsigned long long most_chunks,
+                                                     unsigned long long& chunk, unsigned long long& nchunks) {
+    chunk = (nblocks + most_chunks - 1) / most_chunks;
+    if (chunk < 1) chunk = 1;
+    nchunks = (nblocks + chunk - 1) / chunk;
+}
 constexpr int kDeferEntries = 1 << 22;   // 16-byte deferral entries in a single-matrix workspace
 // FP32-bulk keeps a float result only over at least this many minors: a float
 // minor carries a relative error up to about u_f times its condition, which

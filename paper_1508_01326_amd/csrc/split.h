@@ -87,4 +87,14 @@ __host__ __device__ inline void split_unrank(unsigned long long j, int n, int si
     c[P - 1] = v;
 }
 
+// Blocks of about K minors (colex_run(r, K) prefixes each) that the side-s
+// prefixes with last column v are cut into.
+template <int P>
+__host__ __device__ inline unsigned long long split_blocks_at(int n, int side, int v, unsigned K,
+                                                              const unsigned long long* bt, int stride) {
+    const unsigned long long cnt = split_count<P>(n, side, v, bt, stride);
+    const unsigned long long k = (unsigned long long)colex_run(n - 1 - v, K);
+    return (cnt + k - 1) / k;
+}
+
 }  // namespace radic

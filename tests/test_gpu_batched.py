@@ -179,5 +179,9 @@ def test_autotune_on_own_batch():
     check(mats, B.results(), "fp32_bulk")        # the last tuning run's results
     res = radic.radic_det_batched(B, "fp32_bulk")
     check(mats, res, "fp32_bulk")
-    chunk, _ = radic.host_batch_chunking(0, 8, 18, spl)
+    # the tuned size sets the chunking: blocks of 64 * spl minors for the float
+    # 8 x 18 matrix, rank windows of at least 64 * spl for an int32 9 x 17
+    chunk, k = radic.host_batch_chunking(0, 8, 18, spl)
+    assert (k - 1) * chunk < radic.host_split_blocks(8, 18, 64 * spl) <= k * chunk
+    chunk, _ = radic.host_batch_chunking(1, 9, 17, spl)
     assert chunk >= 64 * spl
