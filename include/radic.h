@@ -393,8 +393,8 @@ int radic_host_unrank(int m, int n, uint64_t q, int *hCols);
 int radic_host_prime(int i, uint32_t *hPrime);
 /* How radic_det_batched cuts the rank space of one matrix (dtype 0 float64,
  * 1 int32) into chunks, the unit a wave takes from its class queue (the
- * granularity scheme of Section 5).  Float matrices with m >= 3 and int32
- * matrices with 3 <= m <= 6 are taken in the two-sided blocks of radic_det
+ * granularity scheme of Section 5).  Float matrices with m >= 7 and int32
+ * matrices with 5 <= m <= 6 are taken in the two-sided blocks of radic_det
  * (radic_host_split_blocks with 64 * subsets_per_lane minors per block):
  * *hChunk blocks per chunk.  The others are cut into rank windows: *hChunk
  * ranks per chunk (a multiple of 64, at least 64 * subsets_per_lane).

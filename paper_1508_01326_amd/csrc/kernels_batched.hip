@@ -408,10 +408,11 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
 }
 
 // ---------------------------------------------------------------- float chunks, prefix-shared (m >= 3)
-// From m = 3 a float chunk is a run of the matrix's two-sided blocks (as the
-// single-matrix kernels take a whole rank space, see split_shape), each worked
-// by the prefix-shared round: the minors of a prefix (first m-2 columns of its
-// side) share its elimination steps and end with a 2 x 2 determinant.  FP32-bulk
+// From m = 3 a float chunk runs the prefix-shared round of the single-matrix
+// kernels: the minors of a prefix (first m-2 columns of its side) share its
+// elimination steps and end with a 2 x 2 determinant.  From m = 7 the chunk is
+// a run of the matrix's two-sided blocks (as the single-matrix kernels take a
+// whole rank space, see split_shape), below a rank window in dictionary order.  FP32-bulk
 // queues its flagged minors in the wave's LDS and refactors them in double by
 // lane groups (between rounds once the queue is half full, and at the end of
 // the chunk); a round whose flagged minors would not fit is done again in
@@ -475,17 +476,22 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     if (restage) stage_float_shared<M, F32>(J, d, L, lane);
     const int n = d.n;
     // the chunk is the run [b0, b1) of the matrix's two-sided blocks, each
-    // taken as by the single-matrix kernel (its whole rank space, no clipping)
+    // taken as by the single-matrix kernel (its whole rank space, no clipping),
+    // or (mt.blocks == 0) the rank window [R0, R1) in dictionary order, the
+    // round clipping its minors to it
+    // (a function of the class, so each class kernel holds one of the two)
+    constexpr bool blocks = batch_uses_blocks(0, M);
     const unsigned K = 64u * (unsigned)(J.spl_float > 0 ? J.spl_float : 1);
     const unsigned long long b0 = c * mt.chunk;
-    const unsigned long long b1 = b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks;
+    const unsigned long long b1 = blocks ? (b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks) : b0 + 1;
+    const unsigned long long R1 = b0 + mt.chunk < mt.total ? b0 + mt.chunk : mt.total;
     FloatJob FJ{};
     FJ.n = n;
-    FJ.q_begin = 0;
-    FJ.count = mt.total;
+    FJ.q_begin = blocks ? 0ull : b0;
+    FJ.count = blocks ? mt.total : R1 - b0;
     FJ.total = mt.total;
     FJ.tau = J.tau;
-    FJ.colex = 1;
+    FJ.colex = blocks ? 1 : 0;
     FJ.colex_pairs = K;
     FJ.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
     FJ.cap = kBatchSharedCap;
@@ -504,10 +510,17 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     unsigned minors;
     const bool f32 = F32 && !mt.all_double;
     for (unsigned long long blk = b0; blk < b1; ++blk) {
-        unsigned long long next;
-        int cnt, side, vlast;
-        split_block<M - 2>(blk, n, bt, kBatchBS, K, lane, side, vlast, next, cnt);
-        const unsigned long long pi1 = next + (unsigned long long)cnt;
+        unsigned long long next, pi1;
+        int side = 0, vlast = 0;
+        if constexpr (blocks) {
+            int cnt;
+            split_block<M - 2>(blk, n, bt, kBatchBS, K, lane, side, vlast, next, cnt);
+            pi1 = next + (unsigned long long)cnt;
+        } else {
+            // the prefixes holding the window's first and last ranks
+            next = prefix_of_rank<M>(b0, n, bt, kBatchBS);
+            pi1 = prefix_of_rank<M>(R1 - 1, n, bt, kBatchBS) + 1;
+        }
         if constexpr (F32) {
             if (f32) {
                 while (next < pi1) {
@@ -599,9 +612,9 @@ __global__ __launch_bounds__(kBatchWaves * kWave) void k_batch_float(BatchJob J)
 
 // ---------------------------------------------------------------- exact chunks
 // Exact chunks share elimination steps: the minors of a prefix (first m-2
-// columns, two-sided blocks) for 3 <= m < kGroupExactMin, of a group (first m-3
-// columns, rank windows) from there to m = 10 (groups hold C(r, 3) minors
-// against C(r, 2) per prefix).
+// columns; rank windows for m = 3, 4, two-sided blocks for 5 <= m <
+// kGroupExactMin), of a group (first m-3 columns, rank windows) from there to
+// m = 10 (groups hold C(r, 3) minors against C(r, 2) per prefix).
 // projected-column slots (16 bytes) per wave: enough for 64 prefixes or groups
 // of the narrow matrices a batch holds
 template <int M> constexpr int batch_cap() { return M >= kGroupExactMin ? 512 : 256; }
@@ -651,11 +664,22 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
     } else if constexpr (M >= 3 && M <= 10) {
         // prefix-shared: the chunk is the run [b0, b1) of the matrix's
         // two-sided blocks, each its whole rank space's as in the single-matrix
-        // kernel
+        // kernel, or (mt.blocks == 0) the rank window [R0, R1), prefixes from
+        // the one holding R0 in dictionary order
+        constexpr bool blocks = batch_uses_blocks(1, M);   // a function of the class
         const unsigned K = 64u * (unsigned)(J.spl_int > 0 ? J.spl_int : 1);
         const unsigned long long b0 = c * mt.chunk;
-        const unsigned long long b1 = b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks;
-        const unsigned long long n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
+        const unsigned long long b1 = blocks ? (b0 + mt.chunk < mt.blocks ? b0 + mt.chunk : mt.blocks) : b0 + 1;
+        const unsigned long long R1 = b0 + mt.chunk < mt.total ? b0 + mt.chunk : mt.total;
+        PrefixSpace sp;
+        sp.n = n;
+        sp.total = mt.total;
+        sp.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];
+        unsigned long long first = 0, rbase = 0;
+        if constexpr (!blocks) {
+            first = prefix_of_rank<M>(b0, n, bt, RADIC_MAX_M);
+            rbase = first_completion_rank<M>(first, sp, bt, RADIC_MAX_M);
+        }
         for (int pi = 0; pi < mt.n_primes; ++pi) {
             const double p = g_prime[pi], pinv = g_prime_inv[pi];
             wave_lds_sync();
@@ -667,13 +691,18 @@ __device__ void int_chunk(const BatchJob& J, const radic_matrix_desc& d, const B
             }
             wave_lds_sync();
             double acc = 0.0;
-            for (unsigned long long blk = b0; blk < b1; ++blk) {
-                unsigned long long next;
-                int cnt, side, vlast;
-                split_block<M - 2>(blk, n, bt, RADIC_MAX_M, K, lane, side, vlast, next, cnt);
-                int_prefix_range<M, true>(L.cr, n, bt, RADIC_MAX_M, next, next + (unsigned long long)cnt, n_prefix,
-                                          0ull, 0ull, mt.total, p, pinv, batch_cap<M>(), L.slot, L.incl, L.tv, lane,
-                                          acc, side, vlast);
+            if constexpr (blocks) {
+                for (unsigned long long blk = b0; blk < b1; ++blk) {
+                    unsigned long long next;
+                    int cnt, side, vlast;
+                    split_block<M - 2>(blk, n, bt, RADIC_MAX_M, K, lane, side, vlast, next, cnt);
+                    int_prefix_range<M, true>(L.cr, n, bt, RADIC_MAX_M, next, next + (unsigned long long)cnt,
+                                              sp.n_prefix, 0ull, 0ull, mt.total, p, pinv, batch_cap<M>(), L.slot,
+                                              L.incl, L.tv, lane, acc, side, vlast);
+                }
+            } else {
+                int_prefix_range<M>(L.cr, n, bt, RADIC_MAX_M, first, sp.n_prefix, sp.n_prefix, rbase, b0, R1, p, pinv,
+                                    batch_cap<M>(), L.slot, L.incl, L.tv, lane, acc);
             }
 #pragma unroll
             for (int o = kWave / 2; o > 0; o >>= 1) acc = addmod(acc, __shfl_xor(acc, o, kWave), p);

@@ -64,10 +64,12 @@ constexpr int kBatchChunksPerMatrix = 256;
 // determinant per minor) from this m on, up to m = 10.
 constexpr int kGroupExactMin = 7;
 // Batched matrices whose chunks are runs of the two-sided blocks of the
-// single-matrix kernels (float m >= 3, exact 3 <= m < kGroupExactMin); the
-// others are cut into rank windows.
-__host__ __device__ inline bool batch_uses_blocks(int kind, int m) {
-    return kind == 0 ? m >= 3 : (m >= 3 && m < kGroupExactMin);
+// single-matrix kernels (float m >= 7, exact 5 <= m < kGroupExactMin); the
+// others are cut into rank windows.  For smaller m a batch matrix (n <= 64)
+// has few prefixes per last column, and blocks, which never span two last
+// columns, would leave most lanes of a round idle.
+__host__ __device__ constexpr bool batch_uses_blocks(int kind, int m) {
+    return kind == 0 ? m >= 7 : (m >= 5 && m < kGroupExactMin);
 }
 // Chunks of a matrix taken in two-sided blocks: runs of chunk blocks, at most
 // most_chunks of them.

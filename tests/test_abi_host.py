@@ -207,14 +207,14 @@ def test_batch_chunking_bounds():
     # rank space exactly once; float matrices have at most 256 chunks, int32 at
     # most 2^16, so a class queue over 2^24 matrices stays far below 2^63 and its
     # 64-bit counter cannot wrap
-    # matrices taken in two-sided blocks (float m >= 3, int32 3 <= m <= 6): the
+    # matrices taken in two-sided blocks (float m >= 7, int32 5 <= m <= 6): the
     # chunks are runs of blocks that cover the block list exactly once
     for dtype in (0, 1):
         for m, n in [(1, 1), (2, 24), (10, 24), (6, 40), (12, 64), (11, 64), (3, 64), (10, 64), (5, 24)]:
             for spl in (1, 4, 8, 64):
                 chunk, k = radic.host_batch_chunking(dtype, m, n, spl)
                 total = math.comb(n, m)
-                blocks = m >= 3 and (dtype == 0 or m <= 6)
+                blocks = m >= 7 if dtype == 0 else 5 <= m <= 6
                 if blocks:
                     nb = radic.host_split_blocks(m, n, 64 * spl)
                     assert chunk >= 1 and (k - 1) * chunk < nb <= k * chunk
