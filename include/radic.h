@@ -64,7 +64,7 @@ typedef enum {
     RADIC_EINVAL = -1,      /* null pointer, m < 1, n < 1, lda < n, bad enum */
     RADIC_ENOTSUP = -2,     /* m > RADIC_MAX_M, n > RADIC_MAX_N, shape too big for on-chip staging */
     RADIC_EOVERFLOW = -3,   /* C(n, m) >= 2^63, or an output buffer too small for the exact result */
-    RADIC_ENOMEM = -4,      /* host allocation failed (library bookkeeping only) */
+    RADIC_ENOMEM = -4,      /* host allocation failed (bookkeeping, or a pinned result buffer) */
     RADIC_EDEVICE = -5,     /* a HIP call failed */
     RADIC_EWORKSPACE = -6,  /* workspace null, misaligned or smaller than radic_workspace_bytes */
     RADIC_ENONFINITE = -7   /* a NaN or infinity in a floating-point input (device-detected) */
@@ -161,13 +161,15 @@ size_t radic_workspace_bytes(int kind, int m, int n, int batch);
  * evaluated over all C(n, m) column sequences in dictionary order.
  *   dA     device, m x n float64, row-major, leading dimension lda (elements).
  *   prec   RADIC_FP64 or RADIC_FP32_BULK.
- *   dOut   device, one radic_f64_result.
+ *   dOut   one radic_f64_result in device memory, or in pinned host memory
+ *          (hipHostMalloc): a kernel writes it, so read it once the stream has
+ *          synchronised.
  *   dWork  device workspace of at least radic_workspace_bytes(RADIC_WS_DET, m, n, 0) bytes.
  * Asynchronous.  m > n writes value 0 (Definition 3) and returns RADIC_OK.
  * The minors are summed in an order fixed by the shape and the launch shape
- * (in prefix-shared mode, blocks of column prefixes taken in colex order,
- * heaviest first), so repeated calls, eager or replayed from a captured graph,
- * give the same bits.
+ * (in prefix-shared mode, blocks of minors sharing their first or their last
+ * columns, taken over the shared columns' last index upwards, heaviest first),
+ * so repeated calls, eager or replayed from a captured graph, give the same bits.
  * Errors: EINVAL, ENOTSUP, EOVERFLOW, EWORKSPACE, EDEVICE (nothing enqueued
  * except for EDEVICE).  Non-finite entries give dOut->status = ENONFINITE.
  */
@@ -229,9 +231,12 @@ int radic_det_2xn(const double *dA, int64_t n, int64_t lda, radic_f64_result *dO
  *   hMagLen    host, number of significant limbs written (0 for a zero result);
  *              on RADIC_EOVERFLOW the number of limbs needed.
  *   hSign      host, -1, 0 or +1.
- * Synchronous: returns after the result is in host memory.
+ * Synchronous: returns after the result is in host memory.  The last kernel
+ * writes the result into a pinned host buffer of the library's (one per call in
+ * flight, allocated on first need and kept until the process ends), so the
+ * read-back is the wait for the stream and no copy command.
  * Errors: EINVAL, ENOTSUP, EOVERFLOW (C(n,m) too large, or mag_capacity too small),
- * EWORKSPACE, EDEVICE.
+ * EWORKSPACE, ENOMEM (the pinned buffer could not be allocated), EDEVICE.
  */
 int radic_det_int_exact(const int32_t *dA, int m, int n, int64_t lda, uint32_t *hMag,
                         int mag_capacity, int *hMagLen, int *hSign, void *dWork, size_t work_bytes,

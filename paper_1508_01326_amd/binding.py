@@ -7,6 +7,7 @@ loudly when the library has not been built.
 """
 import ctypes
 import os
+import threading
 
 import numpy as np
 
@@ -176,13 +177,33 @@ def workspace(kind, m=0, n=0, batch=0, device=None):
     return torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
 
 
-def new_f64_result(device=None):
+def new_f64_result(device=None, pinned=False):
+    """A radic_f64_result buffer in device memory, or (pinned=True) in pinned
+    host memory, which the library's kernel writes directly."""
     torch = _torch()
+    if pinned:
+        return torch.zeros(F64_RESULT_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
     return torch.zeros(F64_RESULT_DTYPE.itemsize, dtype=torch.uint8, device=device or "cuda")
 
 
+_per_thread = threading.local()
+
+
+def _result_buffer(out, sync, device):
+    """The caller's buffer; else, for a synchronous call, this thread's pinned
+    host buffer (the result needs no copy back), or a new device buffer."""
+    if out is not None:
+        return out
+    if not sync:
+        return new_f64_result(device)
+    buf = getattr(_per_thread, "f64_result", None)
+    if buf is None:
+        buf = _per_thread.f64_result = new_f64_result(pinned=True)
+    return buf
+
+
 def read_f64_result(out):
-    raw = out.cpu().numpy().tobytes()
+    raw = (out.cpu() if out.is_cuda else out).numpy().tobytes()
     r = np.frombuffer(raw, dtype=F64_RESULT_DTYPE)[0]
     return {k: (r[k].item()) for k in F64_RESULT_DTYPE.names if k != "reserved"}
 
@@ -194,7 +215,7 @@ def radic_det(A, precision="fp64", out=None, work=None, stream=None, sync=True):
     torch = _torch()
     m, n, lda = _matrix_args(A, torch.float64)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    out = out if out is not None else new_f64_result(A.device)
+    out = _result_buffer(out, sync, A.device)
     work = work if work is not None else workspace(RADIC_WS_DET, max(m, 1), max(n, 1), device=A.device)
     rc = lib().radic_det(ctypes.c_void_p(A.data_ptr()), m, n, lda, prec, ctypes.c_void_p(out.data_ptr()),
                          ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_handle(stream))
@@ -213,7 +234,7 @@ def radic_det_2xn(A, out=None, work=None, stream=None, sync=True):
     if A.dim() != 2 or A.shape[0] != 2 or A.stride(1) != 1:
         raise ValueError("A must be a 2 x n matrix with unit column stride")
     n, lda = A.shape[1], A.stride(0)
-    out = out if out is not None else new_f64_result(A.device)
+    out = _result_buffer(out, sync, A.device)
     work = work if work is not None else workspace(RADIC_WS_DET, 2, 2, device=A.device)
     rc = lib().radic_det_2xn(ctypes.c_void_p(A.data_ptr()), n, lda, ctypes.c_void_p(out.data_ptr()),
                              ctypes.c_void_p(work.data_ptr()), work.numel(), _stream_handle(stream))
@@ -228,7 +249,7 @@ def radic_det_range(A, q_begin, count, precision="fp64", out=None, work=None, st
     torch = _torch()
     m, n, lda = _matrix_args(A, torch.float64)
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-    out = out if out is not None else new_f64_result(A.device)
+    out = _result_buffer(out, sync, A.device)
     work = work if work is not None else workspace(RADIC_WS_DET, max(m, 1), max(n, 1), device=A.device)
     rc = lib().radic_det_range(ctypes.c_void_p(A.data_ptr()), m, n, lda, prec, int(q_begin), int(count),
                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(work.data_ptr()),

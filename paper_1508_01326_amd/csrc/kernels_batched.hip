@@ -832,31 +832,30 @@ __global__ __launch_bounds__(256) void k_batch_finalize(BatchJob J) {
         r.abs_sum = ldexp(ab, mt.scale_exp);
         r.value = r.hi + r.lo;
         r.n_fallback = nfb;
-    } else if (mt.kind == 1 && lane == 0) {
-        unsigned long long res[RADIC_MAX_PRIMES], pr[RADIC_MAX_PRIMES];
-        for (int i = 0; i < mt.n_primes; ++i) {
-            pr[i] = (unsigned long long)g_prime[i];
-            res[i] = J.residues[(size_t)b * RADIC_MAX_PRIMES + i] % pr[i];
-        }
-        unsigned mag[RADIC_MAX_PRIMES + 1];
+    } else if (mt.kind == 1) {
+        // the whole wave: Chinese remaindering with lane i on prime i
+        const int k = mt.n_primes;
+        const int li = lane < k ? lane : 0;
+        const unsigned long long pr = (unsigned long long)g_prime[li];
+        const double res = lane < k ? (double)(J.residues[(size_t)b * RADIC_MAX_PRIMES + lane] % pr) : 0.0;
         int sign = 0, len = 0;
-        crt_to_limbs(res, pr, mt.n_primes, sign, len, mag);
-        r.n_primes = mt.n_primes;
+        unsigned limb = 0;
+        wave_crt(res, k, lane, sign, len, limb);
+        r.n_primes = k;
         r.sign = sign;
         if (len > RADIC_MAX_PRIMES) {
             r.status = RADIC_EOVERFLOW;
         } else {
             r.mag_len = len;
             double v = 0.0;
-            for (int l = len - 1; l >= 0; --l) {
-                r.mag[l] = mag[l];
-                v = v * 4294967296.0 + (double)mag[l];
+#pragma unroll
+            for (int l = RADIC_MAX_PRIMES - 1; l >= 0; --l) {
+                r.mag[l] = l < len ? (unsigned)__shfl((int)limb, l, kWave) : 0u;
+                if (l < len) v = v * 4294967296.0 + (double)r.mag[l];
             }
             r.value = sign < 0 ? -v : v;
             r.hi = r.value;
         }
-    } else if (mt.kind == 0 || mt.kind == 1) {
-        return;
     } else if (mt.status == RADIC_ENONFINITE) {
         r.value = __builtin_nan("");
     }

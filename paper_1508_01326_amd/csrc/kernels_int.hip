@@ -54,27 +54,39 @@ template <int M> __host__ __device__ int int_lds_bytes(int n) {
 __global__ __launch_bounds__(256) void k_int_bound(const int* A, int m, int n, long long lda, IntHeader* h,
                                                    int prime_count) {
     __shared__ double norms[RADIC_MAX_N];
+    __shared__ double lg[RADIC_MAX_PRIMES];
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        double a[RADIC_MAX_M];
+#pragma unroll
+        for (int i = 0; i < RADIC_MAX_M; ++i) a[i] = i < m ? (double)A[(long long)i * lda + j] : 0.0;
         double s = 0.0;
-        for (int i = 0; i < m; ++i) {
-            const double a = (double)A[(long long)i * lda + j];
-            s = __builtin_fma(a, a, s);
-        }
+#pragma unroll
+        for (int i = 0; i < RADIC_MAX_M; ++i) s = __builtin_fma(a[i], a[i], s);
         norms[j] = sqrt(s) * (1.0 + 1e-12);   // rounded up
     }
+    if ((int)threadIdx.x < prime_count) lg[threadIdx.x] = log2(g_prime[threadIdx.x]);
     __syncthreads();
     if (threadIdx.x == 0) {
-        // e_m of the column norms by the recurrence e_k += x e_{k-1} (all terms >= 0)
+        // e_m of the column norms by the recurrence e_k += x e_{k-1} (all terms
+        // >= 0), held in registers: the k loop is unrolled to the largest m
         double e[RADIC_MAX_M + 1];
         e[0] = 1.0;
-        for (int k = 1; k <= m; ++k) e[k] = 0.0;
-        for (int j = 0; j < n; ++j)
-            for (int k = m; k >= 1; --k) e[k] = __builtin_fma(norms[j], e[k - 1], e[k]);
-        const double bound = e[m] * (1.0 + 1e-9) + 1.0;
+#pragma unroll
+        for (int k = 1; k <= RADIC_MAX_M; ++k) e[k] = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double x = norms[j];
+#pragma unroll
+            for (int k = RADIC_MAX_M; k >= 1; --k)
+                if (k <= m) e[k] = __builtin_fma(x, e[k - 1], e[k]);
+        }
+        double em = 0.0;
+#pragma unroll
+        for (int k = 0; k <= RADIC_MAX_M; ++k) em = k == m ? e[k] : em;
+        const double bound = em * (1.0 + 1e-9) + 1.0;
         const double need = log2(bound) + 1.0 + 1e-6;   // product of primes > 2 * bound
         double have = 0.0;
         int k = 0;
-        while (k < prime_count && have <= need) have += log2(g_prime[k++]);
+        while (k < prime_count && have <= need) have += lg[k++];
         h->bound_log2 = log2(bound);
         h->n_primes = k;
         h->status = have > need ? RADIC_OK : RADIC_EOVERFLOW;
@@ -244,47 +256,48 @@ __global__ __launch_bounds__(kMaxBlock) void k_radic_int_shared(IntSharedJob J) 
 }
 
 // ---------------------------------------------------------------- CRT
-// Sum the workgroup residues per prime (every thread takes a strided share;
-// the residues are below 2^31 and there are at most 8192 per prime, so the
-// 64-bit integer sums are exact), then Garner's algorithm (mixed radix digits
-// v_i with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...), then the symmetric
-// representative in (-P/2, P/2] as sign and 32-bit limbs.
+// Sum the workgroup residues per prime (a wave per prime; the residues are
+// below 2^31 and there are at most 8192 per prime, so the 64-bit integer sums
+// are exact), then, on one wave, Garner's algorithm (mixed radix digits v_i
+// with S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ...) and the symmetric representative
+// in (-P/2, P/2] as sign and 32-bit limbs.
 // `launched`: the primes the modular kernel was launched for (an upper bound on
 // the bound kernel's count; a larger count would leave residues missing).
 __global__ __launch_bounds__(256) void k_int_finalize(const double* partials, int grid_x, int launched,
                                                       const IntHeader* h, IntResult* out) {
-    __shared__ unsigned long long res[RADIC_MAX_PRIMES];
-    __shared__ unsigned long long red[256 / kWave];
-    const int k = h->n_primes <= launched ? h->n_primes : 0;
+    __shared__ double res[RADIC_MAX_PRIMES];
     const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, waves = blockDim.x / kWave;
-    for (int t = 0; t < k; ++t) {
+    const bool counted = h->n_primes <= launched;
+    const int k = counted ? h->n_primes : 0;
+    // one wave per prime: the workgroups' residues summed exactly in 64 bits,
+    // four loads in flight per lane
+    for (int t = wave; t < k; t += waves) {
+        const double* row = partials + (long long)t * grid_x;
         unsigned long long s = 0;
-        for (int b = threadIdx.x; b < grid_x; b += blockDim.x) s += (unsigned long long)partials[(long long)t * grid_x + b];
+        int b = lane;
+        for (; b + 3 * kWave < grid_x; b += 4 * kWave)
+            s += (unsigned long long)row[b] + (unsigned long long)row[b + kWave] +
+                 (unsigned long long)row[b + 2 * kWave] + (unsigned long long)row[b + 3 * kWave];
+        for (; b < grid_x; b += kWave) s += (unsigned long long)row[b];
         for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kWave);
-        if (lane == 0) red[wave] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long tot = 0;
-            for (int w = 0; w < waves; ++w) tot += red[w];
-            res[t] = tot % (unsigned long long)g_prime[t];
-        }
-        __syncthreads();
+        if (lane == 0) res[t] = (double)(s % (unsigned long long)g_prime[t]);
     }
-    if (threadIdx.x != 0) return;
-    IntResult r{};
-    r.n_primes = k;
-    r.status = h->n_primes <= launched ? h->status : RADIC_EDEVICE;
-    if (r.status != RADIC_OK) {
-        *out = r;
-        return;
+    __syncthreads();
+    if (wave != 0) return;
+    const int status = counted ? h->status : RADIC_EDEVICE;
+    const bool ok = status == RADIC_OK && k > 0;
+    const double r = lane < k ? res[lane] : 0.0;
+    int sign = 0, len = 0;
+    unsigned limb = 0;
+    if (ok) wave_crt(r, k, lane, sign, len, limb);
+    if (lane <= RADIC_MAX_PRIMES) out->mag[lane] = ok && lane < len ? limb : 0u;
+    if (lane < RADIC_MAX_PRIMES) out->residue[lane] = ok && lane < k ? (unsigned)r : 0u;
+    if (lane == 0) {
+        out->status = status;
+        out->sign = sign;
+        out->mag_len = len;
+        out->n_primes = k;
     }
-    unsigned long long pr[RADIC_MAX_PRIMES];
-    for (int i = 0; i < k; ++i) {
-        pr[i] = (unsigned long long)g_prime[i];
-        r.residue[i] = (unsigned)res[i];
-    }
-    crt_to_limbs(res, pr, k, r.sign, r.mag_len, r.mag);
-    *out = r;
 }
 
 // ---------------------------------------------------------------- host side
@@ -293,7 +306,6 @@ hipError_t upload_binomials_int(const unsigned long long* host_table) { return u
 hipError_t upload_primes(const unsigned* primes, int count) { return upload_prime_table(primes, count); }
 
 size_t int_header_bytes() { return 256; }
-size_t int_result_offset() { return 256; }
 size_t int_partials_offset() { return 1024; }
 size_t int_workspace_bytes() { return int_partials_offset() + sizeof(double) * (size_t)RADIC_MAX_PRIMES * kMaxGrid; }
 size_t int_result_size() { return sizeof(IntResult); }
@@ -382,12 +394,12 @@ hipError_t launch_int_shared(const int* A, int m, int n, long long lda, unsigned
     }
 }
 
-hipError_t launch_int_finalize(int grid_x, int launched, void* ws, hipStream_t s) {
+hipError_t launch_int_finalize(int grid_x, int launched, void* ws, void* out, hipStream_t s) {
     unsigned char* w = static_cast<unsigned char*>(ws);
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_int_finalize, dim3(1), dim3(256), 0, s,
                        reinterpret_cast<const double*>(w + int_partials_offset()), grid_x, launched,
-                       reinterpret_cast<const IntHeader*>(w), reinterpret_cast<IntResult*>(w + int_result_offset()));
+                       reinterpret_cast<const IntHeader*>(w), static_cast<IntResult*>(out));
     return hipGetLastError();
 }
 

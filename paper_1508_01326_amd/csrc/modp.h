@@ -154,81 +154,72 @@ __device__ __forceinline__ void frac_add(double& n1, double& d1, double n2, doub
     d1 = mulmod(d1, d2, p, pinv);
 }
 
-// Chinese remaindering of residues res[i] mod pr[i] (the first k primes of the
-// uploaded set, whose Garner inverses are in g_garner_inv),
-// Garner's mixed-radix form: S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ..., then the
-// representative in (-P/2, P/2], P = prod p_i, written as sign (-1, 0, 1) and
-// little-endian 32-bit limbs mag[0..len-1] (mag holds at least k + 1 limbs).
-__device__ inline void crt_to_limbs(const unsigned long long* res, const unsigned long long* pr, int k, int& sign,
-                                    int& len_out, unsigned* mag) {
-    unsigned long long v[RADIC_MAX_PRIMES];
-    for (int i = 0; i < k; ++i) {
-        // value of the digits found so far mod p_i, times the uploaded inverse of
-        // the product of the earlier primes (pr is the uploaded prime set)
-        unsigned long long t = 0;
-        for (int j = i - 1; j >= 0; --j) t = (t * (pr[j] % pr[i]) + v[j]) % pr[i];
-        const unsigned long long diff = (res[i] % pr[i] + pr[i] - t) % pr[i];
-        v[i] = i == 0 ? res[0] % pr[0] : (diff * g_garner_inv[i]) % pr[i];
+// ---------------------------------------------------------------- Chinese remaindering (one wave)
+// Multi-limb integers across a wave: lane l holds 32-bit limb l (little-endian).
+// Carries between limbs by lookahead on the wave's ballots: with bit l of g set
+// where limb l produces a carry by itself and bit l of q where it passes an
+// incoming one on, the carries into the limbs are those of the binary sum
+// (g | q) + g.  The same rule gives borrows.
+__device__ __forceinline__ unsigned long long carries_in(unsigned long long g, unsigned long long q) {
+    const unsigned long long x = g | q;
+    return (x + g) ^ x ^ g;
+}
+
+// s * mult + add for mult, add < 2^31; the result must fit in the wave's limbs.
+__device__ __forceinline__ unsigned limbs_mul_add(unsigned s, unsigned mult, unsigned add, int lane) {
+    const unsigned long long prod = (unsigned long long)s * mult;
+    const unsigned hi_below = __shfl_up((unsigned)(prod >> 32), 1, kWave);
+    const unsigned long long sum = (prod & 0xffffffffull) + (lane == 0 ? add : hi_below);   // < 2^33
+    const unsigned c_below = __shfl_up((unsigned)(sum >> 32), 1, kWave);
+    const unsigned long long y = (sum & 0xffffffffull) + (lane == 0 ? 0u : c_below);          // <= 2^32
+    const unsigned long long cin = carries_in(__ballot((y >> 32) != 0), __ballot(y == 0xffffffffull));
+    return (unsigned)y + (unsigned)((cin >> lane) & 1ull);
+}
+
+// a - b for a >= b.
+__device__ __forceinline__ unsigned limbs_sub(unsigned a, unsigned b, int lane) {
+    const unsigned long long bin = carries_in(__ballot(a < b), __ballot(a == b));
+    return a - b - (unsigned)((bin >> lane) & 1ull);
+}
+
+// The integer in (-P/2, P/2], P = p_0 p_1 ... p_{k-1} (the first k primes of
+// the uploaded set), with residue r (exact double in [0, p_i)) on lane i < k.
+// Garner's mixed-radix digits, v_i = (r_i - sum_{j<i} v_j p_0...p_{j-1})
+// (p_0...p_{i-1})^-1 mod p_i, are found one per step, lane i keeping its
+// running sum; then S = v_0 + v_1 p_0 + v_2 p_0 p_1 + ... (Horner) and P as
+// limbs, and S - P when 2S > P.  Called by every lane of a wave with the same k
+// (1 <= k <= RADIC_MAX_PRIMES); returns sign (-1, 0, 1), the number of
+// significant limbs, and limb `lane` of the magnitude.
+__device__ inline void wave_crt(double r, int k, int lane, int& sign, int& len, unsigned& limb) {
+    const bool own = lane < k;
+    const int li = own ? lane : 0;
+    const double p = g_prime[li], pinv = g_prime_inv[li];
+    double t = 0.0, w = 1.0, v = 0.0;   // running sum mod p_lane; p_0...p_{j-1} mod p_lane; digit
+    for (int j = 0; j < k; ++j) {
+        if (lane == j) v = mulmod(submod(r, t, p), (double)g_garner_inv[j], p, pinv);
+        const double vj = __shfl(v, j, kWave);
+        if (own && lane > j) {
+            t = addmod(t, mulmod(canon(vj, p, pinv), w, p, pinv), p);
+            w = mulmod(w, canon(g_prime[j], p, pinv), p, pinv);
+        }
     }
-    // S = v_{k-1}; S = S * p_i + v_i (Horner, 32-bit limbs); P = prod p_i
-    unsigned S[RADIC_MAX_PRIMES + 1] = {0}, Pm[RADIC_MAX_PRIMES + 1] = {0};
-    int len = 0, plen = 1;
-    Pm[0] = 1;
-    for (int i = k - 1; i >= 0; --i) {
-        unsigned long long carry = v[i];
-        for (int l = 0; l < len; ++l) {
-            const unsigned long long cur = (unsigned long long)S[l] * pr[i] + carry;
-            S[l] = (unsigned)cur;
-            carry = cur >> 32;
-        }
-        while (carry) {
-            S[len++] = (unsigned)carry;
-            carry >>= 32;
-        }
+    unsigned s = 0, pm = lane == 0 ? 1u : 0u;
+    for (int i = k - 1; i >= 0; --i) s = limbs_mul_add(s, (unsigned)g_prime[i], (unsigned)__shfl(v, i, kWave), lane);
+    for (int i = 0; i < k; ++i) pm = limbs_mul_add(pm, (unsigned)g_prime[i], 0u, lane);
+    // compare 2S with P (P is odd, so they differ)
+    const unsigned s_below = __shfl_up(s, 1, kWave);
+    const unsigned s2 = (s << 1) | (lane == 0 ? 0u : s_below >> 31);
+    const unsigned long long diff = __ballot(s2 != pm);
+    bool above = false;
+    if (diff) {
+        const int top = 63 - __builtin_clzll(diff);
+        above = __shfl(s2, top, kWave) > __shfl(pm, top, kWave);
     }
-    for (int i = 0; i < k; ++i) {
-        unsigned long long carry = 0;
-        for (int l = 0; l < plen; ++l) {
-            const unsigned long long cur = (unsigned long long)Pm[l] * pr[i] + carry;
-            Pm[l] = (unsigned)cur;
-            carry = cur >> 32;
-        }
-        while (carry) {
-            Pm[plen++] = (unsigned)carry;
-            carry >>= 32;
-        }
-    }
-    // compare 2S with P
-    unsigned S2[RADIC_MAX_PRIMES + 2] = {0};
-    int s2len = len;
-    {
-        unsigned carry = 0;
-        for (int l = 0; l < len; ++l) {
-            S2[l] = (S[l] << 1) | carry;
-            carry = S[l] >> 31;
-        }
-        if (carry) S2[s2len++] = carry;
-    }
-    int cmp = 0;
-    if (s2len != plen) cmp = s2len > plen ? 1 : -1;
-    else
-        for (int l = plen - 1; l >= 0 && cmp == 0; --l)
-            if (S2[l] != Pm[l]) cmp = S2[l] > Pm[l] ? 1 : -1;
-    sign = len == 0 ? 0 : 1;
-    if (cmp > 0) {   // S > P/2: the value is S - P < 0; magnitude P - S
-        long long borrow = 0;
-        for (int l = 0; l < plen; ++l) {
-            long long cur = (long long)Pm[l] - (l < len ? (long long)S[l] : 0) - borrow;
-            borrow = cur < 0;
-            S[l] = (unsigned)(cur + (borrow ? (1ll << 32) : 0));
-        }
-        len = plen;
-        sign = -1;
-    }
-    while (len > 0 && S[len - 1] == 0) --len;
-    if (len == 0) sign = 0;
-    len_out = len;
-    for (int l = 0; l < len; ++l) mag[l] = S[l];
+    const unsigned mag = above ? limbs_sub(pm, s, lane) : s;
+    const unsigned long long nz = __ballot(mag != 0u);
+    len = nz ? 64 - __builtin_clzll(nz) : 0;
+    sign = len == 0 ? 0 : (above ? -1 : 1);
+    limb = mag;
 }
 
 }  // namespace radic

@@ -33,7 +33,7 @@ hipError_t upload_primes(const unsigned* primes, int count);
 hipError_t launch_int_bound(const int* A, int m, int n, long long lda, void* ws, int prime_count, hipStream_t s);
 hipError_t launch_int_main(const int* A, int m, int n, long long lda, unsigned long long count, int spl,
                            int grid_x, int n_primes, int block, void* ws, hipStream_t s);
-hipError_t launch_int_finalize(int grid_x, int launched, void* ws, hipStream_t s);
+hipError_t launch_int_finalize(int grid_x, int launched, void* ws, void* out, hipStream_t s);
 int int_shared_lds(int m, int n, int waves, int cap);
 size_t run_bytes();
 hipError_t launch_2xn(const double* A, long long lda, long long n, int G, void* runs, void* flag,
@@ -52,7 +52,6 @@ void host_batch_chunking(int kind, unsigned long long total, int spl, unsigned l
 hipError_t launch_batched(const radic_matrix_desc* desc, int batch, const double* f64, const int* i32, int prec,
                           double tau, int spl_float, int spl_int, int prime_count, radic_batch_result* out,
                           void* ws, hipStream_t s);
-size_t int_result_offset();
 size_t int_result_size();
 int int_lds(int m, int n);
 int float_lds_bytes(int m, int n, int prec, int waves);
@@ -753,6 +752,35 @@ static int int_prime_upper_bound(int m, int n, const std::vector<unsigned>& prim
     return std::min((int)primes.size(), k + 1);
 }
 
+// Pinned host buffers for the exact result: the CRT kernel writes the result
+// straight into one, so reading it back needs no copy command, only the wait
+// for the stream.  A pool holds one buffer per call in flight; buffers live as
+// long as the process.
+static std::mutex g_pin_mu;
+static std::vector<void*> g_pin_free;
+
+struct PinnedResult {
+    void* p = nullptr;
+    PinnedResult() {
+        {
+            std::lock_guard<std::mutex> lk(g_pin_mu);
+            if (!g_pin_free.empty()) {
+                p = g_pin_free.back();
+                g_pin_free.pop_back();
+                return;
+            }
+        }
+        if (hipHostMalloc(&p, int_result_size(), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    }
+    ~PinnedResult() {
+        if (!p) return;
+        std::lock_guard<std::mutex> lk(g_pin_mu);
+        g_pin_free.push_back(p);
+    }
+    PinnedResult(const PinnedResult&) = delete;
+    PinnedResult& operator=(const PinnedResult&) = delete;
+};
+
 extern "C" {
 
 const char* radic_status_string(int status) {
@@ -874,6 +902,8 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
     const int prime_count = (int)primes.size();
     Shape sh = pick_shape(RADIC_WS_INT, 0, m, n);
     if (int_lds(m, n) > kMaxLds) return RADIC_ENOTSUP;
+    PinnedResult pinned;
+    if (!pinned.p) return host_error(RADIC_ENOMEM, "pinned buffer for the exact result");
     // 1. bound -> number of primes, on the device; the modular kernel is
     // launched for an upper bound on it that needs no look at A (entries below
     // 2^31 in magnitude), and the primes it does not need exit at once, so the
@@ -912,19 +942,17 @@ int radic_det_int_exact(const int32_t* dA, int m, int n, int64_t lda, uint32_t* 
         e = launch_int_main(dA, m, n, lda, total, sh.spl, grid, k, sh.block, dWork, stream);
     }
     if (e != hipSuccess) return device_error("launch of the modular kernel", e);
-    e = launch_int_finalize(grid, k, dWork, stream);
+    e = launch_int_finalize(grid, k, dWork, pinned.p, stream);
     if (e != hipSuccess) return device_error("launch of the CRT kernel", e);
-    std::vector<unsigned char> res(int_result_size());
-    e = hipMemcpyAsync(res.data(), static_cast<unsigned char*>(dWork) + int_result_offset(), res.size(),
-                       hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return device_error("read-back of the exact result", e);
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return device_error("wait for the exact result", e);
+    const unsigned char* res = static_cast<const unsigned char*>(pinned.p);
     int fields[4];
-    std::memcpy(fields, res.data(), sizeof(fields));   // status, sign, mag_len, n_primes
+    std::memcpy(fields, res, sizeof(fields));   // status, sign, mag_len, n_primes
     if (fields[0] != RADIC_OK) return fields[0];
     *hMagLen = fields[2];
     if (fields[2] > mag_capacity) return RADIC_EOVERFLOW;
-    std::memcpy(hMag, res.data() + sizeof(fields), sizeof(uint32_t) * (size_t)fields[2]);
+    std::memcpy(hMag, res + sizeof(fields), sizeof(uint32_t) * (size_t)fields[2]);
     *hSign = fields[1];
     return RADIC_OK;
 }
