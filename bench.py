@@ -36,7 +36,7 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # sources hash to the same value.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "split.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "09589147ad462395235aa8079d3805615dcb9514a492f17949a1e62396b89a8f", "fp64": 410440, "fp32_bulk": 2533232}
+PROFILED_TRAFFIC = {"sources_sha256": "67810ce820238069430fbb336004d469de7a3007114473747915a93f57c0b260", "fp64": 410440, "fp32_bulk": 2533232}
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
 PROFILED_FLOPS = {"fp64": {"fp32": 1476992, "fp64": 251909632}, "fp32_bulk": {"fp32": 208400000, "fp64": 138810240}}
 # VALU wave instructions per launch (SQ_INSTS_VALU) on the same sources

@@ -68,17 +68,26 @@ __global__ __launch_bounds__(256) void k_int_bound(const int* A, int m, int n, l
     __syncthreads();
     if (threadIdx.x == 0) {
         // e_m of the column norms by the recurrence e_k += x e_{k-1} (all terms
-        // >= 0), held in registers: the k loop is unrolled to the largest m
+        // >= 0), held in registers: the k loop is unrolled to the largest m with
+        // no test of k against m (e_k for k > m never enters e_m), the column
+        // loop by four so that the norms' LDS reads overlap
         double e[RADIC_MAX_M + 1];
         e[0] = 1.0;
 #pragma unroll
         for (int k = 1; k <= RADIC_MAX_M; ++k) e[k] = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double x = norms[j];
+        auto step = [&](double x) {
 #pragma unroll
-            for (int k = RADIC_MAX_M; k >= 1; --k)
-                if (k <= m) e[k] = __builtin_fma(x, e[k - 1], e[k]);
+            for (int k = RADIC_MAX_M; k >= 1; --k) e[k] = __builtin_fma(x, e[k - 1], e[k]);
+        };
+        int j = 0;
+        for (; j + 4 <= n; j += 4) {
+            const double x0 = norms[j], x1 = norms[j + 1], x2 = norms[j + 2], x3 = norms[j + 3];
+            step(x0);
+            step(x1);
+            step(x2);
+            step(x3);
         }
+        for (; j < n; ++j) step(norms[j]);
         double em = 0.0;
 #pragma unroll
         for (int k = 0; k <= RADIC_MAX_M; ++k) em = k == m ? e[k] : em;
