@@ -56,6 +56,42 @@ def test_extreme_entries():
     assert abs(got).bit_length() > 200     # needs many primes
 
 
+def _sylvester(k):
+    H = np.array([[1]], dtype=np.int64)
+    for _ in range(k):
+        H = np.block([[H, H], [H, -H]])
+    return H
+
+
+@pytest.mark.parametrize("exchange", [False, True])
+def test_hadamard_bound_attained(exchange):
+    # A Sylvester-Hadamard matrix of order 8 scaled by 2^31 - 1 attains the
+    # bound the prime count is chosen from (Hadamard's inequality is an
+    # equality): |det| = 8^4 (2^31 - 1)^8, about 2^260, nine 32-bit limbs; an
+    # exchange of two rows flips the sign (m = n: the Radic determinant is the
+    # ordinary one, Definition 3)
+    H = _sylvester(3) * (2 ** 31 - 1)
+    if exchange:
+        H = H[[1, 0, 2, 3, 4, 5, 6, 7]]
+    A = H.astype(np.int32)
+    got = run_int(A, f"hadamard 8x8 exchange={exchange}")
+    assert abs(got) == 8 ** 4 * (2 ** 31 - 1) ** 8
+    assert got == oracle.radic_int(A)
+    B = _sylvester(3) * (2 ** 31 - 1)
+    assert got == (-1 if exchange else 1) * oracle.radic_int(B.astype(np.int32))
+
+
+def test_hadamard_rows_wide():
+    # the same rows with two more columns of extreme entries: 45 minors, most
+    # near the bound, summed with both signs
+    rng = np.random.default_rng(11)
+    A = np.concatenate([_sylvester(3) * (2 ** 31 - 1),
+                        rng.integers(-2 ** 31, 2 ** 31, size=(8, 2), dtype=np.int64)], axis=1).astype(np.int32)
+    got = run_int(A, "hadamard rows 8x10")
+    assert got == oracle.radic_int(A) == exact.radic_subset_dp(A)
+    assert abs(got).bit_length() > 240
+
+
 def test_zero_pivots_and_structure():
     # leading zero columns force exchanges; equal rows give exactly zero
     A = np.array([[0, 0, 1, 2, 3, 0], [0, 1, 0, 4, 5, 0], [1, 0, 0, 6, 7, 0]], dtype=np.int32)
