@@ -36,11 +36,11 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # sources hash to the same value.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "split.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "67810ce820238069430fbb336004d469de7a3007114473747915a93f57c0b260", "fp64": 410440, "fp32_bulk": 2533232}
+PROFILED_TRAFFIC = {"sources_sha256": "f4c9caddde8c7b57370908062363f1e7361b5cd2495607321c063c1da659fdd5", "fp64": 410440, "fp32_bulk": 1084701}
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
-PROFILED_FLOPS = {"fp64": {"fp32": 1476992, "fp64": 251909632}, "fp32_bulk": {"fp32": 208400000, "fp64": 138810240}}
+PROFILED_FLOPS = {"fp64": {"fp32": 1476992, "fp64": 251909632}, "fp32_bulk": {"fp32": 208400000, "fp64": 89097024}}
 # VALU wave instructions per launch (SQ_INSTS_VALU) on the same sources
-PROFILED_VALU = {"fp64": 13570755, "fp32_bulk": 19972537}
+PROFILED_VALU = {"fp64": 13570755, "fp32_bulk": 17040446}
 # wave-instruction issue rate of the VALUs: 256 CU x 4 SIMD x 2.4 GHz, one
 # 64-lane instruction per SIMD every 4 clocks (16 lanes per clock)
 PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4

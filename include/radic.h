@@ -73,8 +73,9 @@ typedef enum {
 typedef enum {
     RADIC_FP64 = 0,      /* every minor factored in IEEE double */
     RADIC_FP32_BULK = 1  /* minors factored in float on rows pre-scaled by exact powers of two;
-                            minors whose product of capped pivot ratios falls below tau are
-                            refactored in double; all accumulation in double.  A call (or a
+                            minors whose product of capped pivot ratios falls below the
+                            threshold (radic_set_fallback_tau) are refactored in double;
+                            all accumulation in double.  A call (or a
                             batch matrix) over fewer than 4096 minors refactors every minor
                             in double (n_fallback = its minor count): only a sum over many
                             minors absorbs the float error within the tolerance */
@@ -327,11 +328,17 @@ int radic_tune_load(const char *path);
 /* Force a launch shape (0 = tuned/default) for subsequent calls; for tests and sweeps. */
 int radic_set_launch(int subsets_per_lane, int block_size);
 /* FP32_BULK fallback threshold tau (default 2^-10): a minor is refactored in double
- * when prod_k min(1, |u_kk| / s_k) < tau, with u_kk the float pivots and s_k the
+ * when prod_k min(1, |u_kk| / s_k) < tau', with u_kk the float pivots and s_k the
  * largest |entry| of the minor's k-th column in the row-scaled matrix (so it also
- * fires whenever a single pivot ratio is below tau).  tau = 0 disables the
- * fallback, tau = +inf refactors every minor. */
+ * fires whenever a single pivot ratio is below tau').  A sum over N minors (a
+ * radic_det or radic_det_range call, or one batch matrix) uses
+ * tau' = tau * min(1, (8192 / N)^(1/4)): the errors of the minors kept in float
+ * add up with independent signs, so their share of sum |det| falls as N grows.
+ * radic_det_subsets, whose terms are not summed, uses tau' = tau.  tau = 0
+ * disables the fallback, tau = +inf refactors every minor. */
 int radic_set_fallback_tau(double tau);
+/* The threshold tau' a sum over `minors` minors uses under the current setting. */
+double radic_fallback_tau_for(uint64_t minors);
 
 /*
  * Which enumeration radic_det / radic_det_range use for float matrices.

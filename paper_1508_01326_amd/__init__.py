@@ -13,4 +13,5 @@ from .binding import (  # noqa: F401
     radic_det_int_exact, radic_det_range, radic_det_subsets, set_fallback_tau, set_launch, set_prime_set, status_string, workspace,
     RADIC_ENUM_AUTO, RADIC_ENUM_PER_MINOR, RADIC_ENUM_PREFIX_SHARED, RADIC_ENUM_GROUP_SHARED, set_enumeration, radic_det_2xn,
     host_batch_chunking, host_split_blocks, host_split_count, host_split_prefix, radic_det_batched_noalloc,
+    fallback_tau_for,
 )

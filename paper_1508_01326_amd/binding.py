@@ -81,6 +81,7 @@ SIGNATURES = {
     "radic_tune_load": (_i, [ctypes.c_char_p]),
     "radic_set_launch": (_i, [_i, _i]),
     "radic_set_fallback_tau": (_i, [_d]),
+    "radic_fallback_tau_for": (_d, [_u64]),
     "radic_set_enumeration": (_i, [_i]),
     "radic_det_2xn": (_i, [_vp, _i64, _i64, _vp, _vp, _sz, _vp]),
     "radic_profile_enable": (_i, [_i]),
@@ -332,6 +333,11 @@ def set_launch(subsets_per_lane=0, block_size=0):
 
 def set_fallback_tau(tau):
     _check(lib().radic_set_fallback_tau(float(tau)), "radic_set_fallback_tau")
+
+
+def fallback_tau_for(minors):
+    """The FP32-bulk threshold a sum over `minors` minors uses under the current setting."""
+    return lib().radic_fallback_tau_for(int(minors))
 
 
 ENUMERATIONS = {"auto": RADIC_ENUM_AUTO, "per_minor": RADIC_ENUM_PER_MINOR,

@@ -337,7 +337,7 @@ __device__ void float_chunk(const BatchJob& J, const radic_matrix_desc& d, const
     const int n = d.n;
     const T* colbase = F32 ? reinterpret_cast<const T*>(L.cf) : reinterpret_cast<const T*>(L.cd);
     const int colstride = F32 ? ST32 : ST64;
-    const T tau = mt.all_double ? (T)__builtin_inf() : (T)J.tau;
+    const T tau = mt.all_double ? (T)__builtin_inf() : (T)effective_tau(J.tau, mt.total);
     const unsigned long long sub = mt.chunk / kWave;          // ranks per lane
     const unsigned long long q0 = c * mt.chunk + (unsigned long long)lane * sub;
     const int cnt = q0 < mt.total ? (int)((mt.total - q0) < sub ? (mt.total - q0) : sub) : 0;
@@ -490,7 +490,7 @@ __device__ void float_chunk_shared(const BatchJob& J, const radic_matrix_desc& d
     FJ.q_begin = blocks ? 0ull : b0;
     FJ.count = blocks ? mt.total : R1 - b0;
     FJ.total = mt.total;
-    FJ.tau = J.tau;
+    FJ.tau = effective_tau(J.tau, mt.total);
     FJ.colex = blocks ? 1 : 0;
     FJ.colex_pairs = K;
     FJ.n_prefix = g_binom[(n - 2) * kBinomCols + (M - 2)];

@@ -561,7 +561,7 @@ static int det_range_impl(const double* dA, int m, int n, long long lda, int pre
     J.chunks = (count + sh.spl - 1) / sh.spl;
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        J.tau = g_tau;
+        J.tau = effective_tau(g_tau, count);
     }
     J.header = reinterpret_cast<DetHeader*>(ws);
     J.partials = reinterpret_cast<Partial*>(ws + ws_partials());
@@ -1328,6 +1328,11 @@ int radic_set_fallback_tau(double tau) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_tau = tau;
     return RADIC_OK;
+}
+
+double radic_fallback_tau_for(uint64_t minors) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    return effective_tau(g_tau, minors);
 }
 
 int radic_profile_enable(int on) {

@@ -87,6 +87,18 @@ constexpr int kDeferEntries = 1 << 22;   // 16-byte deferral entries in a single
 // fewer minors refactors every minor in double (threshold tau = +inf).
 constexpr unsigned long long kF32MinMinors = 4096;
 
+// The threshold an FP32-bulk sum over `minors` minors uses, from the set tau:
+// the errors of the minors kept in float add up with independent signs, so
+// their share of sum |det| falls as the count grows, and the threshold falls
+// with the fourth root of the count beyond kTauMinors (on uniformly
+// ill-conditioned matrices this kept the worst error near its level at 8192
+// minors).  0 (never) and +inf (always) are kept as they are.
+constexpr double kTauMinors = 8192.0;
+__host__ __device__ inline double effective_tau(double tau, unsigned long long minors) {
+    if (!(tau > 0.0) || tau > 1.7976931348623157e308 || (double)minors <= kTauMinors) return tau;
+    return tau * sqrt(sqrt(kTauMinors / (double)minors));
+}
+
 // Per-workgroup partial of a floating-point enumeration (32 bytes).
 struct Partial {
     double hi;

@@ -126,6 +126,28 @@ def _is_prime(n):
     return True
 
 
+def test_fallback_threshold_scaling():
+    # tau' = tau * min(1, (8192 / N)^(1/4)); exact at powers of two of N / 8192
+    L = radic.lib()
+    t = 1.0 / 1024
+    assert L.radic_set_fallback_tau(t) == radic.RADIC_OK
+    try:
+        assert radic.fallback_tau_for(1) == t
+        assert radic.fallback_tau_for(8192) == t
+        assert radic.fallback_tau_for(8192 * 16) == t / 2
+        assert radic.fallback_tau_for(8192 * 2 ** 16) == t / 16
+        assert t / 2 < radic.fallback_tau_for(8192 * 16 - 1) < t
+        N = 10518300   # C(32, 8)
+        assert abs(radic.fallback_tau_for(N) - t * (8192 / N) ** 0.25) <= 1e-18
+        # never and always stay as set
+        assert L.radic_set_fallback_tau(0.0) == radic.RADIC_OK
+        assert radic.fallback_tau_for(10 ** 12) == 0.0
+        assert L.radic_set_fallback_tau(float("inf")) == radic.RADIC_OK
+        assert radic.fallback_tau_for(10 ** 12) == float("inf")
+    finally:
+        assert L.radic_set_fallback_tau(t) == radic.RADIC_OK
+
+
 def test_default_prime_set():
     primes = [radic.host_prime(i) for i in range(radic.binding.RADIC_MAX_PRIMES)]
     assert primes == sorted(primes, reverse=True)

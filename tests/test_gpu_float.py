@@ -239,6 +239,21 @@ def test_fallback_near_dependent_rows():
     print("error without fallback / S:", abs(bad["value"] - ref["value"]) / S)
 
 
+@pytest.mark.parametrize("m,n,eps", [(6, 16, 1e-3), (7, 20, 3e-4), (7, 20, 1e-3), (8, 24, 1e-4), (9, 24, 3e-4),
+                                     (8, 32, 1e-4)])
+def test_fallback_uniformly_ill_conditioned(m, n, eps):
+    # a row near another makes every minor about eps-conditioned, so the float
+    # errors are not small against sum |det| as for random minors: the
+    # threshold (scaled for the minor count) must still refactor enough of them
+    A = workloads.near_dependent_rows(m, n, seed=40 + m + n, eps=eps)
+    ref = oracle.radic_f64(A)
+    got = run_case(A, "fp32_bulk", f"ill-conditioned {m}x{n} eps={eps:g}")
+    S = max(ref["abs_sum"], 1e-300)
+    err = abs(got["value"] - ref["value"]) / S
+    print(f"error / S = {err:.2e}, refactored {got['n_fallback']} of {math.comb(n, m)}")
+    assert err <= 1e-5
+
+
 def test_fallback_overflow_in_some_workgroups(enum):
     # columns 1 and 2 nearly parallel: every minor holding both (the first
     # C(18, 4) ranks of the dictionary order) is flagged, so the waves that own

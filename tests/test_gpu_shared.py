@@ -215,9 +215,13 @@ def test_fallback_round_overflow():
     S = normaliser(ref["abs_sum"], A)
     got = run(A, "fp64", "8x40 fp64")
     assert_close(got["value"], ref["value"], S, TOL["fp64"], "8x40 fp64")
+    # tau set so that the threshold of this 76.9 M-minor sum is 2^-10
+    N = math.comb(40, 8)
+    radic.set_fallback_tau(2.0 ** -10 * (N / 8192) ** 0.25)
+    assert abs(radic.fallback_tau_for(N) - 2.0 ** -10) < 1e-15
     got = run(A, "fp32_bulk", "8x40 tau=2^-10")
     assert_close(got["value"], ref["value"], S, TOL["fp32_bulk"], "8x40 tau=2^-10")
-    assert 0 < got["n_fallback"] < math.comb(40, 8) // 50
+    assert 0 < got["n_fallback"] < N // 50
     radic.set_fallback_tau(float("inf"))
     got = run(A, "fp32_bulk", "8x40 tau=inf")
     assert got["n_fallback"] == math.comb(40, 8)
