@@ -494,9 +494,13 @@ def main():
     launches = radic.profile_read_launches()
     if dom is None:
         dom = "fp64" if sum(launches[0::2]) >= sum(launches[1::2]) else "fp32_bulk"
-        dom_ms = sum(timed[(0 if dom == "fp64" else 1)::2]) / max(1, len(timed) // 2)
+        dom_times = timed[(0 if dom == "fp64" else 1)::2]
     else:
-        dom_ms = sum(timed) / max(1, len(timed))
+        dom_times = list(timed)
+    dom_ms = sum(dom_times) / max(1, len(dom_times))
+    dom_sorted = sorted(dom_times)
+    dom_median = dom_sorted[len(dom_sorted) // 2] if dom_sorted else None
+    dom_min = dom_sorted[0] if dom_sorted else None
 
     k64 = launches[0::2]
     k32 = launches[1::2]
@@ -572,7 +576,8 @@ def main():
                                                         f"a different method's work"},
                      "rocprof_flops": rocprof_flops(dom, args.enumeration, dom_ms),
                      "valu_issue": valu_issue(dom, args.enumeration, dom_ms),
-                     "kernel_ms": dom_ms, "launches_timed": len(timed),
+                     "kernel_ms": dom_ms, "kernel_ms_median": dom_median, "kernel_ms_min": dom_min,
+                     "launches_timed": len(dom_times),
                      "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},
         "cpu_baseline": cpu,
         "forms": per_form,
