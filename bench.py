@@ -32,15 +32,36 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # HBM bytes per launch of the enumeration kernels on this workload, from
 # rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a 256 MiB reference copy (the
 # summary and commands are in profiles/k_radic_shared_8x32.md).  They hold for
-# the kernel sources they were taken on: `traffic` is reported only while the
-# sources hash to the same value.
+# the kernel sources and the launch shape (subsets per lane, "spl") they were
+# taken on: `traffic` is reported only while the sources hash to the same value
+# and the run uses the same shape.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "split.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "f4c9caddde8c7b57370908062363f1e7361b5cd2495607321c063c1da659fdd5", "fp64": 410440, "fp32_bulk": 1084701}
+PROFILED_TRAFFIC = {"sources_sha256": "8e0789e3744fe15a00580c8dbeceabe7987172840326ede8a5fa20c1ced6df17", "spl": {"fp64": 96, "fp32_bulk": 80}, "fp64": 407080, "fp32_bulk": 1022438}
+# the library's default subsets per lane for the prefix-shared float kernels
+DEFAULT_SPL_SHARED = 64
+# launch shapes written by the library's autotuner (paper_1508_01326_amd/tune_shapes.py)
+TUNED_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1508_01326_amd", "tuned_gfx950.txt")
+ENUM_CODES = {"auto": 0, "per_minor": 1, "prefix_shared": 2, "group_shared": 3}
+
+
+def table_shapes(path, m, n, enumeration):
+    """Subsets per lane per float precision that a launch-shape table gives an
+    m x n matrix under the enumeration (rows: kind prec m n_bucket enumeration
+    spl block; kind 0 is a single float matrix)."""
+    nb = n if n <= 16 else ((n + 7) // 8 * 8 if n <= 64 else (n + 31) // 32 * 32)
+    out = {}
+    with open(path) as f:
+        for line in f:
+            v = line.split()
+            if (len(v) == 7 and v[0] == "0" and v[1] in ("0", "1") and int(v[2]) == m and int(v[3]) == nb
+                    and int(v[4]) == ENUM_CODES[enumeration]):
+                out["fp64" if v[1] == "0" else "fp32_bulk"] = int(v[5])
+    return out
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
-PROFILED_FLOPS = {"fp64": {"fp32": 1476992, "fp64": 251909632}, "fp32_bulk": {"fp32": 208400000, "fp64": 89097024}}
+PROFILED_FLOPS = {"fp64": {"fp32": 1395712, "fp64": 254986560}, "fp32_bulk": {"fp32": 204090112, "fp64": 87046528}}
 # VALU wave instructions per launch (SQ_INSTS_VALU) on the same sources
-PROFILED_VALU = {"fp64": 13570755, "fp32_bulk": 17040446}
+PROFILED_VALU = {"fp64": 13701482, "fp32_bulk": 16581212}
 # wave-instruction issue rate of the VALUs: 256 CU x 4 SIMD x 2.4 GHz, one
 # 64-lane instruction per SIMD every 4 clocks (16 lanes per clock)
 PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4
@@ -337,17 +358,24 @@ def per_minor_roofline(radic, A, outs, work, torch):
     return res
 
 
-def traffic_for(form, enumeration):
-    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+def profiled(form, enumeration, spl):
+    """The profiled figures hold for this run: the same kernel sources, the
+    prefix-shared enumeration and the same subsets per lane (block size)."""
+    return (enumeration in ("auto", "prefix_shared") and spl == PROFILED_TRAFFIC["spl"][form]
+            and kernel_sources_sha256() == PROFILED_TRAFFIC["sources_sha256"])
+
+
+def traffic_for(form, enumeration, spl):
+    if not profiled(form, enumeration, spl):
         return None
     return PROFILED_TRAFFIC[form]
 
 
-def rocprof_flops(form, enumeration, kernel_ms):
+def rocprof_flops(form, enumeration, spl, kernel_ms):
     """FLOPs per launch of the prefix-shared kernel from its rocprofv3 counters
     (SQ_INSTS_VALU_FLOPS_FP32/FP64 x 64), over this run's kernel time; None
-    once the kernel sources differ from those profiled."""
-    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+    once the kernel sources or the launch shape differ from those profiled."""
+    if not profiled(form, enumeration, spl):
         return None
     f = PROFILED_FLOPS[form]
     peak = PEAK_FP32_TFLOPS if form == "fp32_bulk" else PEAK_FP64_TFLOPS
@@ -358,13 +386,13 @@ def rocprof_flops(form, enumeration, kernel_ms):
             "source": "rocprofv3 counters per launch (profiles/k_radic_shared_8x32.md)"}
 
 
-def valu_issue(form, enumeration, kernel_ms):
+def valu_issue(form, enumeration, spl, kernel_ms):
     """VALU wave instructions per launch of the prefix-shared kernel from its
     rocprofv3 counter (SQ_INSTS_VALU), over this run's kernel time, against the
     chip's issue rate: the bound these kernels meet, since most of their
-    instructions are not floating point; None once the kernel sources differ
-    from those profiled."""
-    if enumeration not in ("auto", "prefix_shared") or kernel_sources_sha256() != PROFILED_TRAFFIC["sources_sha256"]:
+    instructions are not floating point; None once the kernel sources or the
+    launch shape differ from those profiled."""
+    if not profiled(form, enumeration, spl):
         return None
     v = PROFILED_VALU[form]
     rate = v / (kernel_ms * 1e-3)
@@ -392,6 +420,10 @@ def main():
     ap.add_argument("--no-other", action="store_true",
                     help="skip the other workloads (5x14 latency, exact 6x40 int32, 12x36 precision stress, "
                          "4096-matrix batch) and the per-minor kernels' roofline")
+    ap.add_argument("--tune", choices=["table", "live", "none"], default="table",
+                    help="launch shapes for the 8x32 shape: the committed table written by the library's "
+                         "autotuner (paper_1508_01326_amd/tuned_gfx950.txt, default), radic_autotune in this "
+                         "run, or the library's defaults")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="before the steps, run one plain device-to-device copy of this many bytes (a "
                          "known-size reference for the HBM byte counters of a profiler run)")
@@ -420,6 +452,19 @@ def main():
     stream = torch.cuda.current_stream()
     print(f"[bench] workload 8x32, {total} minors, steps={args.steps} warmup={args.warmup}", file=sys.stderr,
           flush=True)
+    # launch shapes for this shape in each precision, chosen by the library's
+    # autotuner: from the table it wrote on this architecture (the same shapes
+    # in every run, profiler runs included), or timed in this run
+    tuned = {}
+    if args.tune == "table" and os.path.exists(TUNED_TABLE):
+        radic.tune_load(TUNED_TABLE)
+        tuned = table_shapes(TUNED_TABLE, m, n, args.enumeration)
+    elif args.tune == "live":
+        for p in ("fp64", "fp32_bulk"):
+            tuned[p] = radic.autotune(radic.RADIC_WS_DET, m, n, p)[0]
+    spl_used = {p: tuned.get(p, DEFAULT_SPL_SHARED) for p in ("fp64", "fp32_bulk")}
+    shape_source = {p: (args.tune if p in tuned else "default") for p in ("fp64", "fp32_bulk")}
+    print(f"[bench] subsets per lane: {spl_used} ({shape_source})", file=sys.stderr, flush=True)
 
     if args.copy_bytes > 0:
         # a copy kernel that reads and writes copy_bytes each (an element-wise
@@ -538,6 +583,7 @@ def main():
             "err_over_sum_abs": abs(r["value"] - ref["value"]) / S,
             "tol": 1e-12 if p == "fp64" else 1e-5,
             "n_fallback": r["n_fallback"],
+            "launch_shape": {"subsets_per_lane": spl_used[p], "source": shape_source[p]},
             "kernel_executed_tflops": xflop / (avg * 1e-3) / 1e12,
             "kernel_counted_tflops": flop / (avg * 1e-3) / 1e12,
             "peak_tflops": peak,
@@ -567,15 +613,16 @@ def main():
                    "enumeration": args.enumeration},
         "roofline": {"bound": "alu", "kernel": kernel_name(args.enumeration, dom),
                      "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": traffic_for(dom, args.enumeration),
+                     "traffic": traffic_for(dom, args.enumeration, spl_used[dom]),
                      "per_unit": f"executed {xflop / total:.2f} FLOP per minor (averaged over the launch; "
                                  f"{args.enumeration} enumeration) x {total} minors = {xflop:.4g} FLOP per launch",
                      "counted_equivalent": {"tflops": counted, "frac": counted / peak,
                                             "per_unit": f"counted (2/3) m^3 = {counted_flops_per_minor(m):.2f} "
                                                         f"FLOP per minor x {total} minors = {flop:.4g} FLOP, "
                                                         f"a different method's work"},
-                     "rocprof_flops": rocprof_flops(dom, args.enumeration, dom_ms),
-                     "valu_issue": valu_issue(dom, args.enumeration, dom_ms),
+                     "rocprof_flops": rocprof_flops(dom, args.enumeration, spl_used[dom], dom_ms),
+                     "valu_issue": valu_issue(dom, args.enumeration, spl_used[dom], dom_ms),
+                     "launch_shape": {"subsets_per_lane": spl_used[dom], "source": shape_source[dom]},
                      "kernel_ms": dom_ms, "kernel_ms_median": dom_median, "kernel_ms_min": dom_min,
                      "launches_timed": len(dom_times),
                      "timed_launches": f"the dominant kernel of 1 in {TIME_EVERY} timed steps"},

@@ -297,11 +297,15 @@ int radic_graph_destroy(void *hGraph);
  * Launch-shape tuning (the granularity knob of Section 5).  radic_autotune times
  * candidate (subsets per lane, workgroup size) pairs for the given shape and
  * precision on the current device with HIP events, on a synthetic matrix of
- * that shape, and records the fastest for later calls.  Synchronous.
+ * that shape, and records the fastest for later calls.  Synchronous.  For the
+ * prefix-shared kernels the subsets per lane set the block of minors that
+ * shares its prefixes (64 x subsets per lane; candidates 16 ... 128 for the
+ * float kernels, 8 ... 64 for the exact one) and the workgroup size is fixed.
  * kind: RADIC_WS_DET (prec applies), RADIC_WS_INT or RADIC_WS_BATCHED (m and n
  * ignored; prec 0 or 1 tunes the float classes on a synthetic float batch, prec 2
  * the exact classes on a synthetic int32 batch).  A shape tuned for n serves
- * every n of its bucket (each n up to 16, runs of 8 up to 64, then of 32).
+ * every n of its bucket (each n up to 16, runs of 8 up to 64, then of 32), under
+ * the enumeration (radic_set_enumeration) it was tuned with.
  * hBest (may be null) receives {subsets_per_lane, block_size}.
  * radic_tune_save/load persist the table as text; the table names the device
  * architecture and the library version (radic_version), and radic_tune_load

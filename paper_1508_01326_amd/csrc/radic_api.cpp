@@ -224,7 +224,8 @@ constexpr int kSharedSplInt = 32;
 // Tuned launch shapes, (kind, prec, m, column bucket) -> shape.  A shape is
 // tuned on one n and serves the n of its bucket: every n up to 16, then runs of
 // 8 up to 64, then of 32.
-static std::map<std::tuple<int, int, int, int>, Shape> g_tuned;
+// tuned launch shapes keyed by (kind, precision, m, n bucket, enumeration)
+static std::map<std::tuple<int, int, int, int, int>, Shape> g_tuned;
 static int n_bucket(int n) { return n <= 16 ? n : (n <= 64 ? (n + 7) / 8 * 8 : (n + 31) / 32 * 32); }
 static int g_force_spl = 0, g_force_block = 0;
 static int g_enumeration = RADIC_ENUM_AUTO;
@@ -247,7 +248,8 @@ static Shape pick_shape(int kind, int prec, int m, int n) {
     Shape s = default_shape(kind, prec, m, n);
     {
         std::lock_guard<std::mutex> lk(g_mu);
-        auto it = g_tuned.find(std::make_tuple(kind, prec, m, n_bucket(n)));
+        const int mode = kind == RADIC_WS_BATCHED ? 0 : g_enumeration;
+        auto it = g_tuned.find(std::make_tuple(kind, prec, m, n_bucket(n), mode));
         if (it != g_tuned.end()) {
             s = it->second;
             s.spl_set = true;
@@ -797,7 +799,7 @@ const char* radic_status_string(int status) {
     }
 }
 
-int radic_version(void) { return 100; }
+int radic_version(void) { return 101; }
 
 const char* radic_last_error(void) { return g_last_error; }
 
@@ -1102,8 +1104,9 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
     DeviceBuffers buf;
     TuneRng rng(0x5eed0000ull + (unsigned long long)(kind * 1000003 + m * 1009 + n));
     std::function<int()> run;
-    const int spls[] = {1, 2, 4, 8, 16, 32, 64};
+    std::vector<int> spls = {1, 2, 4, 8, 16, 32, 64};
     std::vector<int> blocks = {64, 128, 256};
+    int reps = 3;
     std::vector<double> hf;
     std::vector<int> hi;
     radic_matrix_desc* dDesc = nullptr;
@@ -1118,6 +1121,15 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
         if (hipMemcpy(dA, hf.data(), hf.size() * 8, hipMemcpyHostToDevice) != hipSuccess) return RADIC_EDEVICE;
         run = [=]() { return radic_det(dA, m, n, n, prec, static_cast<radic_f64_result*>(out), ws,
                                        det_workspace_bytes(m, n), stream); };
+        if (float_enumeration(m, n, prec) == 2) {
+            // prefix-shared: spl sets the two-sided blocks (64 spl minors each),
+            // and with them how the blocks fill the waves; the workgroup size
+            // follows the LDS budget.  Neighbouring sizes differ by a few per
+            // cent, hence the finer steps and more runs per candidate.
+            spls = {16, 24, 32, 40, 48, 56, 64, 80, 96, 128};
+            blocks = {256};
+            reps = 15;
+        }
     } else if (kind == RADIC_WS_INT) {
         hi.resize((size_t)m * n);
         for (int& x : hi) x = (int)(rng.next() % 19) - 9;
@@ -1131,6 +1143,16 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
             return radic_det_int_exact(dA, m, n, n, mag, RADIC_MAX_PRIMES + 1, &len, &sg, ws, int_workspace_bytes(),
                                        stream);
         };
+        int mode;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            mode = g_enumeration;
+        }
+        if (mode != RADIC_ENUM_PER_MINOR && m >= 3 && m <= 10) {   // the prefix-shared exact kernel
+            spls = {8, 16, 24, 32, 40, 48, 64};
+            blocks = {256};
+            reps = 15;
+        }
     } else {
         // a synthetic mixed batch of the shapes the persistent kernels serve (m in [2, 10], n in [m, 24])
         batch = 512;
@@ -1173,7 +1195,7 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
                 g_force_block = block;
             }
             int trc = RADIC_OK;
-            const float ms = time_runs(run, stream, 3, &trc);
+            const float ms = time_runs(run, stream, reps, &trc);
             if (trc != RADIC_OK) continue;
             if (best.spl == 0 || ms < best_ms) {
                 best_ms = ms;
@@ -1187,7 +1209,7 @@ int radic_autotune(int kind, int m, int n, int prec, int* hBest, hipStream_t str
     if (best.spl == 0) return RADIC_EDEVICE;
     const int key_prec = kind == RADIC_WS_DET ? prec : (kind == RADIC_WS_INT ? 0 : prec);
     const int km = kind == RADIC_WS_BATCHED ? 0 : m, kn = kind == RADIC_WS_BATCHED ? 0 : n_bucket(n);
-    g_tuned[std::make_tuple(kind, key_prec, km, kn)] = best;
+    g_tuned[std::make_tuple(kind, key_prec, km, kn, kind == RADIC_WS_BATCHED ? 0 : g_enumeration)] = best;
     if (hBest) {
         hBest[0] = best.spl;
         hBest[1] = best.block;
@@ -1251,8 +1273,8 @@ int radic_autotune_batched(const radic_matrix_desc* dDesc, int batch, const doub
     g_force_spl = saved_spl;
     g_force_block = saved_block;
     if (best == 0) return RADIC_EDEVICE;
-    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, prec, 0, 0)] = Shape{best, kBatchBlock};
-    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, 2, 0, 0)] = Shape{best, kBatchBlock};
+    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, prec, 0, 0, 0)] = Shape{best, kBatchBlock};
+    g_tuned[std::make_tuple((int)RADIC_WS_BATCHED, 2, 0, 0, 0)] = Shape{best, kBatchBlock};
     if (hBest) {
         hBest[0] = best;
         hBest[1] = kBatchBlock;
@@ -1266,11 +1288,11 @@ int radic_tune_save(const char* path) {
     FILE* f = std::fopen(path, "w");
     if (!f) return RADIC_EINVAL;
     std::lock_guard<std::mutex> lk(g_mu);
-    std::fprintf(f, "# radic launch-shape table: kind prec m n_bucket subsets_per_lane block\n");
+    std::fprintf(f, "# radic launch-shape table: kind prec m n_bucket enumeration subsets_per_lane block\n");
     std::fprintf(f, "arch %s version %d\n", arch.c_str(), radic_version());
     for (const auto& kv : g_tuned)
-        std::fprintf(f, "%d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-                     std::get<3>(kv.first), kv.second.spl, kv.second.block);
+        std::fprintf(f, "%d %d %d %d %d %d %d\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
+                     std::get<3>(kv.first), std::get<4>(kv.first), kv.second.spl, kv.second.block);
     return std::fclose(f) == 0 ? RADIC_OK : RADIC_EINVAL;
 }
 
@@ -1278,7 +1300,7 @@ int radic_tune_load(const char* path) {
     if (!path) return RADIC_EINVAL;
     FILE* f = std::fopen(path, "r");
     if (!f) return RADIC_EINVAL;
-    std::map<std::tuple<int, int, int, int>, Shape> t;
+    std::map<std::tuple<int, int, int, int, int>, Shape> t;
     char line[256];
     int rc = RADIC_OK;
     bool header = false;
@@ -1297,13 +1319,13 @@ int radic_tune_load(const char* path) {
             header = true;
             continue;
         }
-        int k, p, m, n, spl, block;
-        if (std::sscanf(line, "%d %d %d %d %d %d", &k, &p, &m, &n, &spl, &block) != 6 || spl < 1 || spl > 4096 ||
-            block < kWave || block > kMaxBlock || block % kWave) {
+        int k, p, m, n, e, spl, block;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d", &k, &p, &m, &n, &e, &spl, &block) != 7 || e < 0 || e > 3 ||
+            spl < 1 || spl > 4096 || block < kWave || block > kMaxBlock || block % kWave) {
             rc = RADIC_EINVAL;
             break;
         }
-        t[std::make_tuple(k, p, m, n)] = Shape{spl, block};
+        t[std::make_tuple(k, p, m, n, e)] = Shape{spl, block};
     }
     std::fclose(f);
     if (rc == RADIC_OK && !header) rc = RADIC_EINVAL;

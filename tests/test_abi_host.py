@@ -198,24 +198,28 @@ def test_int_validation_without_device():
 
 def test_tune_table_roundtrip(tmp_path):
     # the table names the device architecture ("none" without a device, as here)
-    # and the library version; shapes are keyed by column bucket
+    # and the library version; shapes are keyed by column bucket and enumeration
     ver = binding.lib().radic_version()
     src = tmp_path / "in.txt"
-    src.write_text(f"# table\narch none version {ver}\n0 0 8 32 4 128\n0 1 8 32 16 256\n1 0 6 40 8 64\n2 2 0 0 2 256\n")
+    src.write_text(f"# table\narch none version {ver}\n0 0 8 32 0 4 128\n0 0 8 32 1 48 256\n0 1 8 32 0 16 256\n"
+                   f"1 0 6 40 0 8 64\n2 2 0 0 0 2 256\n")
     radic.tune_load(src)
     out = tmp_path / "out.txt"
     radic.tune_save(out)
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
     assert lines[0] == f"arch none version {ver}"
     rows = [l.split() for l in lines[1:]]
-    assert ["0", "0", "8", "32", "4", "128"] in rows
-    assert ["2", "2", "0", "0", "2", "256"] in rows
+    assert ["0", "0", "8", "32", "0", "4", "128"] in rows
+    assert ["0", "0", "8", "32", "1", "48", "256"] in rows
+    assert ["2", "2", "0", "0", "0", "2", "256"] in rows
     bad = tmp_path / "bad.txt"
-    bad.write_text(f"arch none version {ver}\n0 0 8 32 4 96\n")   # block not a multiple of 64
+    bad.write_text(f"arch none version {ver}\n0 0 8 32 0 4 96\n")   # block not a multiple of 64
     with pytest.raises(radic.RadicError):
         radic.tune_load(bad)
-    for text in ("0 0 8 32 4 128\n",                               # no header
-                 f"arch none version {ver + 1}\n0 0 8 32 4 128\n"):   # another library version
+    for text in ("0 0 8 32 0 4 128\n",                               # no header
+                 f"arch none version {ver + 1}\n0 0 8 32 0 4 128\n",    # another library version
+                 f"arch none version {ver}\n0 0 8 32 4 128\n",          # no enumeration column
+                 f"arch none version {ver}\n0 0 8 32 7 4 128\n"):       # no such enumeration
         other = tmp_path / "other.txt"
         other.write_text(text)
         with pytest.raises(radic.RadicError):
