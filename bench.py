@@ -37,7 +37,7 @@ PEAK_FP32_TFLOPS = 157.3   # published vector FP32 peak (packed FP32); unpacked 
 # and the run uses the same shape.
 KERNEL_SOURCES = ["kernels_shared.hip", "shared_round.h", "shared_lu.h", "prefix.h", "split.h", "stage.h", "lu_float.h", "enumerate.h",
                   "radic_internal.h", "radic_api.cpp"]
-PROFILED_TRAFFIC = {"sources_sha256": "8e0789e3744fe15a00580c8dbeceabe7987172840326ede8a5fa20c1ced6df17", "spl": {"fp64": 96, "fp32_bulk": 80}, "fp64": 407080, "fp32_bulk": 1022438}
+PROFILED_TRAFFIC = {"sources_sha256": "0587ed8f1ed234ec4c0fadc60ee478cd891222b0653a10aedb933b55ebdee406", "spl": {"fp64": 48, "fp32_bulk": 80}, "fp64": 415463, "fp32_bulk": 1022437}
 # the library's default subsets per lane for the prefix-shared float kernels
 DEFAULT_SPL_SHARED = 64
 # launch shapes written by the library's autotuner (paper_1508_01326_amd/tune_shapes.py)
@@ -59,9 +59,9 @@ def table_shapes(path, m, n, enumeration):
                 out["fp64" if v[1] == "0" else "fp32_bulk"] = int(v[5])
     return out
 # FLOPs per launch counted by SQ_INSTS_VALU_FLOPS_FP32/FP64 (x 64 lanes) on the same sources
-PROFILED_FLOPS = {"fp64": {"fp32": 1395712, "fp64": 254986560}, "fp32_bulk": {"fp32": 204090112, "fp64": 87046528}}
+PROFILED_FLOPS = {"fp64": {"fp32": 1600000, "fp64": 247332032}, "fp32_bulk": {"fp32": 204090112, "fp64": 87046528}}
 # VALU wave instructions per launch (SQ_INSTS_VALU) on the same sources
-PROFILED_VALU = {"fp64": 13701482, "fp32_bulk": 16581212}
+PROFILED_VALU = {"fp64": 13410005, "fp32_bulk": 16581212}
 # wave-instruction issue rate of the VALUs: 256 CU x 4 SIMD x 2.4 GHz, one
 # 64-lane instruction per SIMD every 4 clocks (16 lanes per clock)
 PEAK_VALU_ISSUE = 256 * 4 * 2.4e9 / 4
